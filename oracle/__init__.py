@@ -1,0 +1,97 @@
+"""Oracle for BFS and integral-weight SSSP -- TEST INFRASTRUCTURE ONLY.
+
+Plain sequential CPU code (``oracle.c``) that defines the expected outputs of
+the GPU library.  Only the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the GPU path: the only common dependency is the seeded input generator
+package ``graphgen``, which holds no traversal arithmetic.
+
+Functions follow the problem statements of the Benchmark section ("Shortest
+Path Problems"), with parents fixed by the minimum-ID rule:
+
+* :func:`bfs`  -- hop distances (int32, INT32_MAX = unreachable) and
+  parent[v] = min{u in N(v): D[u] + 1 == D[v]}, parent[src] = src, -1 if
+  unreachable.
+* :func:`wbfs` -- integral-weight distances (uint32, 0xFFFFFFFF =
+  unreachable), computed with Dial's bucketed Dijkstra, and
+  parent[v] = min{u in N(v): D[u] + w(u,v) == D[v]}.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+BFS_INF = np.int32(2**31 - 1)
+WBFS_INF = np.uint32(0xFFFFFFFF)
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c (plain C, -O2, single-threaded) into liboracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_bfs.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P, P]
+        lib.oracle_bfs.restype = ctypes.c_int
+        lib.oracle_wbfs.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P]
+        lib.oracle_wbfs.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _csr_arrays(g):
+    off = np.ascontiguousarray(g.offsets, dtype=np.int64)
+    nb = np.ascontiguousarray(g.nbrs, dtype=np.int32)
+    if nb.size == 0:
+        nb = np.zeros(1, dtype=np.int32)
+    return off, nb
+
+
+def bfs(g, src: int):
+    """Return (dist int32[n], parent int32[n]) for a BFS from src."""
+    off, nb = _csr_arrays(g)
+    dist = np.empty(g.n, dtype=np.int32)
+    parent = np.empty(g.n, dtype=np.int32)
+    rc = _load().oracle_bfs(g.n, _p(off), _p(nb), int(src), _p(dist), _p(parent))
+    if rc != 0:
+        raise ValueError(f"oracle_bfs failed with code {rc}")
+    return dist, parent
+
+
+def wbfs(g, src: int, weights=None):
+    """Return (dist uint32[n], parent int32[n]) for integral-weight SSSP."""
+    w = g.weights if weights is None else weights
+    if w is None:
+        raise ValueError("weighted graph required")
+    off, nb = _csr_arrays(g)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    if ww.size == 0:
+        ww = np.ones(1, dtype=np.int32)
+    dist = np.empty(g.n, dtype=np.uint32)
+    parent = np.empty(g.n, dtype=np.int32)
+    rc = _load().oracle_wbfs(g.n, _p(off), _p(nb), _p(ww), int(src), _p(dist), _p(parent))
+    if rc != 0:
+        raise ValueError(f"oracle_wbfs failed with code {rc}")
+    return dist, parent

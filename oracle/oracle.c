@@ -1,0 +1,168 @@
+/*
+ * Oracle for single-source BFS and integral-weight SSSP (weighted BFS).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This plain, sequential, single-threaded CPU code
+ * defines the expected results.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may call it; the GPU library never does, and
+ * the two share no code.
+ *
+ * What is computed (problem statements of the Benchmark section, "Shortest
+ * Path Problems"):
+ *   BFS:  D[v] = hop distance from src, infinity when unreachable.
+ *   wBFS: D[v] = shortest-path distance from src with integral weights,
+ *         infinity when unreachable.
+ * Both are reached exactly by the paper's frontier algorithms (BFS and wBFS
+ * algorithm boxes), so the oracle computes the plain definitions with
+ * textbook methods: a FIFO-queue BFS, and Dial's bucketed Dijkstra (buckets
+ * indexed by tentative distance, stale entries skipped when popped).
+ *
+ * The paper's BFS leaves the discovering parent to whichever test-and-set
+ * wins, so it is not unique.  Here the parent is fixed by definition:
+ *   BFS:  parent[v] = min { u in N(v) : D[u] + 1      == D[v] }
+ *   wBFS: parent[v] = min { u in N(v) : D[u] + w(u,v) == D[v] }
+ * with parent[src] = src and parent = -1 for unreachable vertices.
+ *
+ * Encodings of infinity: BFS int32 INT32_MAX, wBFS uint32 0xFFFFFFFF.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define BFS_INF INT32_MAX
+#define WBFS_INF 0xFFFFFFFFu
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
+int oracle_bfs(int64_t n, const int64_t* offsets, const int32_t* nbrs,
+               int32_t src, int32_t* dist, int32_t* parent) {
+    if (n <= 0 || src < 0 || src >= n) return -1;
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!queue) return -2;
+    for (int64_t v = 0; v < n; ++v) {
+        dist[v] = BFS_INF;
+        parent[v] = -1;
+    }
+    /* FIFO breadth-first search: D[src] = 0, each vertex enqueued once, at
+     * the first time it is seen, with the distance of its discoverer + 1. */
+    int64_t head = 0, tail = 0;
+    dist[src] = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+            int32_t v = nbrs[e];
+            if (dist[v] == BFS_INF) {
+                dist[v] = dist[u] + 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    free(queue);
+    /* Parent rule: smallest neighbour one hop closer to the source. */
+    for (int64_t v = 0; v < n; ++v) {
+        if (dist[v] == BFS_INF || v == src) continue;
+        int32_t best = -1;
+        for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
+            int32_t u = nbrs[e];
+            if (dist[u] != BFS_INF && dist[u] + 1 == dist[v] && (best < 0 || u < best))
+                best = u;
+        }
+        parent[v] = best;
+    }
+    parent[src] = src;
+    return 0;
+}
+
+/* Growable int32 list used as one Dial bucket. */
+typedef struct {
+    int32_t* a;
+    int64_t len, cap;
+} ilist;
+
+static int ilist_push(ilist* l, int32_t x) {
+    if (l->len == l->cap) {
+        int64_t nc = l->cap ? 2 * l->cap : 16;
+        int32_t* na = (int32_t*)realloc(l->a, sizeof(int32_t) * (size_t)nc);
+        if (!na) return -1;
+        l->a = na;
+        l->cap = nc;
+    }
+    l->a[l->len++] = x;
+    return 0;
+}
+
+/* Returns 0 on success, -1 on bad arguments (weights < 1), -2 on allocation
+ * failure.  Distances are accumulated in 64 bits and must stay below
+ * 0xFFFFFFFF (guaranteed when max_w * (n - 1) < 2^32 - 1). */
+int oracle_wbfs(int64_t n, const int64_t* offsets, const int32_t* nbrs,
+                const int32_t* w, int32_t src, uint32_t* dist, int32_t* parent) {
+    if (n <= 0 || src < 0 || src >= n) return -1;
+    int64_t m = offsets[n];
+    int64_t maxw = 1;
+    for (int64_t e = 0; e < m; ++e) {
+        if (w[e] < 1) return -1;
+        if (w[e] > maxw) maxw = w[e];
+    }
+    /* Dial's algorithm: tentative distances lie in [cur, cur + maxw], so a
+     * circular array of maxw + 1 buckets holds every pending entry. */
+    const int64_t C = maxw + 1;
+    ilist* bucket = (ilist*)calloc((size_t)C, sizeof(ilist));
+    uint64_t* d = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+    unsigned char* settled = (unsigned char*)calloc((size_t)n, 1);
+    if (!bucket || !d || !settled) {
+        free(bucket); free(d); free(settled);
+        return -2;
+    }
+    const uint64_t INF64 = UINT64_MAX;
+    for (int64_t v = 0; v < n; ++v) d[v] = INF64;
+    d[src] = 0;
+    int64_t pending = 0;
+    int rc = 0;
+    if (ilist_push(&bucket[0], src)) rc = -2;
+    pending = 1;
+    uint64_t cur = 0;
+    while (pending > 0 && rc == 0) {
+        ilist* b = &bucket[cur % (uint64_t)C];
+        /* Entries appended while scanning this bucket carry larger
+         * distances (weights >= 1), so they never land in this bucket. */
+        for (int64_t i = 0; i < b->len; ++i) {
+            int32_t u = b->a[i];
+            --pending;
+            if (settled[u] || d[u] != cur) continue; /* stale entry */
+            settled[u] = 1;
+            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+                int32_t v = nbrs[e];
+                uint64_t nd = cur + (uint64_t)w[e];
+                if (!settled[v] && nd < d[v]) {
+                    d[v] = nd;
+                    if (ilist_push(&bucket[nd % (uint64_t)C], v)) { rc = -2; break; }
+                    ++pending;
+                }
+            }
+        }
+        b->len = 0;
+        ++cur;
+    }
+    for (int64_t i = 0; i < C; ++i) free(bucket[i].a);
+    free(bucket);
+    free(settled);
+    if (rc) { free(d); return rc; }
+    for (int64_t v = 0; v < n; ++v) {
+        dist[v] = d[v] == INF64 ? WBFS_INF : (uint32_t)d[v];
+        parent[v] = -1;
+    }
+    /* Parent rule: smallest neighbour u with D[u] + w(u,v) == D[v]; the
+     * weights are symmetric, so w(u,v) is read from v's own list. */
+    for (int64_t v = 0; v < n; ++v) {
+        if (d[v] == INF64 || v == src) continue;
+        int32_t best = -1;
+        for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
+            int32_t u = nbrs[e];
+            if (d[u] != INF64 && d[u] + (uint64_t)w[e] == d[v] && (best < 0 || u < best))
+                best = u;
+        }
+        parent[v] = best;
+    }
+    parent[src] = src;
+    free(d);
+    return 0;
+}
