@@ -1,0 +1,250 @@
+/*
+ * gbgpu -- frontier traversal (edgeMap) over a resident CSR graph on one
+ * MI355X (gfx950) GPU: breadth-first search and integral-weight SSSP
+ * (weighted BFS), single-source, multi-source batched, and served.
+ *
+ * Operations follow the problem statements of the paper's Benchmark section,
+ * "Shortest Path Problems" (Dhulipala, Blelloch, Shun, "Theoretically
+ * Efficient Parallel Graph Algorithms Can Be Fast and Scalable"):
+ *   BFS:  input G = (V, E) unweighted and src; output D[v] = hop distance
+ *         from src, infinity if unreachable.
+ *   wBFS: input G = (V, E, w) with integral weights and src; output D[v] =
+ *         shortest-path distance, infinity if unreachable.
+ * The paper's BFS lets a test-and-set pick the discovering parent, so its
+ * parent is not unique; this library fixes it deterministically:
+ *   BFS:  parent[v] = min { u in N(v) : D[u] + 1      == D[v] }
+ *   wBFS: parent[v] = min { u in N(v) : D[u] + w(u,v) == D[v] }
+ *   parent[src] = src; parent[v] = -1 when v is unreachable.
+ * Output encodings: BFS dist int32 with INT32_MAX for infinity; wBFS dist
+ * uint32 with 0xFFFFFFFF for infinity; parent int32.
+ *
+ * Conventions for every call:
+ *   - Return value is a gbgpu_status; 0 (GBGPU_OK) means success.  On any
+ *     other value gbgpu_last_error() returns a message for the calling thread.
+ *   - Argument errors are detected before any device work; outputs are then
+ *     left untouched.
+ *   - "dev" pointers are device pointers on the current HIP device (for
+ *     instance torch tensor data); "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is ordered on that stream; the traversal calls return only when
+ *     their outputs are complete.
+ *   - Graph handles are immutable after load and may be shared between
+ *     threads; calls on one handle are serialised internally because they
+ *     share its workspace.
+ */
+#ifndef GBGPU_H
+#define GBGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GBGPU_OK = 0,
+    GBGPU_E_INVALID = 1,     /* bad argument or malformed graph            */
+    GBGPU_E_UNSUPPORTED = 2, /* valid input outside this build's limits    */
+    GBGPU_E_NOMEM = 3,       /* device or host allocation failed / budget  */
+    GBGPU_E_HIP = 4,         /* HIP runtime error                          */
+    GBGPU_E_OVERFLOW = 5,    /* distances could exceed 0xFFFFFFFF - 1      */
+    GBGPU_E_AGAIN = 6,       /* not ready yet / queue full; retry later    */
+    GBGPU_E_NOTFOUND = 7     /* unknown ticket or id                       */
+} gbgpu_status;
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* gbgpu_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int gbgpu_version(void);
+
+typedef struct gbgpu_graph_s* gbgpu_graph;
+
+/* Load flags. */
+enum {
+    GBGPU_SYMMETRIC = 1u, /* caller asserts every edge is stored both ways   */
+    GBGPU_VALIDATE = 2u   /* check the CSR on the device (see gbgpu_load_csr) */
+};
+
+/* Tuning knobs; a zero field selects the built-in (or autotuned) default.
+ * None of them changes results, only speed. */
+typedef struct {
+    int32_t force_direction; /* 0 auto, 1 always push (sparse), 2 always pull
+                                (dense), 3 alternate push/pull by round       */
+    int32_t tau;             /* go dense when |U| + sum deg(U) > m / tau       */
+    int32_t pull_light;      /* pull: neighbours one lane scans before the
+                                vertex is handed to a whole wavefront          */
+    int32_t wave_chunk;      /* push: max edges per wavefront work item (>=64) */
+    int32_t grid;            /* workgroups per traversal launch                */
+    int32_t bucket_window;   /* wBFS: ring of buckets (power of two >= 2*maxw+1) */
+    int32_t bucket_capacity; /* wBFS: entries per bucket (retried larger on
+                                overflow)                                       */
+    int32_t rounds_per_sync; /* launches issued between host completion checks */
+    int32_t profile;         /* 1: time each traversal launch with HIP events   */
+    int32_t reserved[7];
+} gbgpu_opts;
+
+/* Per-call statistics (optional out-parameter). */
+typedef struct {
+    int32_t rounds;          /* BFS rounds / wBFS buckets processed            */
+    int32_t push_rounds;     /* rounds run sparse (push)                       */
+    int32_t pull_rounds;     /* rounds run dense (pull)                        */
+    int32_t launches;        /* traversal kernel launches issued               */
+    int64_t reached;         /* vertices with finite distance                  */
+    int64_t edges_examined;  /* sum of deg over processed frontiers            */
+    double kernel_ms;        /* sum of traversal kernel times (profile = 1)    */
+    double wall_ms;          /* host wall time of the call                     */
+    int32_t retries;         /* wBFS reruns after a bucket overflow            */
+    int32_t reserved[7];
+} gbgpu_stats;
+
+/* Register a CSR graph that already lives in device memory.
+ *   n          number of vertices, 0 < n < 2^31
+ *   m          number of stored (directed) entries, 0 <= m < 2^32
+ *   offsets    dev int64[n+1], offsets[0] = 0, offsets[n] = m, non-decreasing
+ *   neighbors  dev int32[m], each list sorted strictly ascending (no
+ *              duplicates), no self loops, ids in [0, n)
+ *   weights    dev int32[m] aligned with neighbors, all >= 1, w(u,v) = w(v,u);
+ *              NULL for an unweighted graph (BFS only)
+ *   flags      must include GBGPU_SYMMETRIC (the dense pull reads a vertex's
+ *              own list as its in-edges); GBGPU_VALIDATE checks every property
+ *              above, including symmetry of edges and weights, on the device
+ *   stream     stream used for the load-time kernels
+ *   out        receives the handle
+ * Ownership: the graph arrays are borrowed -- the caller keeps them alive and
+ * unchanged until gbgpu_graph_free.  The handle owns a degree array, a
+ * zero-degree bitmap and lazily sized traversal workspaces.
+ * Errors: E_INVALID for null pointers, bad sizes, a missing SYMMETRIC flag or
+ * a failed validation; E_UNSUPPORTED for n or m beyond the limits above. */
+int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets,
+                   const int32_t* neighbors, const int32_t* weights,
+                   uint32_t flags, void* stream, gbgpu_graph* out);
+
+/* Release a handle and its workspaces (not the borrowed arrays). */
+int gbgpu_graph_free(gbgpu_graph g);
+
+/* Number of vertices / stored entries / maximum weight (0 if unweighted). */
+int gbgpu_graph_info(gbgpu_graph g, int64_t* n, int64_t* m, int32_t* max_weight);
+
+/* Single-source BFS (BFS problem statement; frontier rounds of edgeMap as in
+ * the paper's BFS algorithm box, with the sparse/dense switch of Ligra's
+ * edgeMap and the blocked sparse traversal of the "edgeMapBlocked" section).
+ *   src     source vertex in [0, n)
+ *   dist    dev int32[n] output, INT32_MAX for unreachable
+ *   parent  dev int32[n] output, min-ID parent, -1 for unreachable
+ *   o, st   optional (NULL allowed)
+ * Errors: E_INVALID for a null handle/output or src out of range. */
+int gbgpu_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+              const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
+/* Single-source integral-weight SSSP (weighted BFS problem statement; the
+ * paper's wBFS algorithm box: buckets by distance, edgeMapData relaxations
+ * with priority-write).
+ *   dist    dev uint32[n] output, 0xFFFFFFFF for unreachable
+ *   parent  dev int32[n] output, min-ID tight parent, -1 for unreachable
+ * Errors: E_INVALID (no weights, bad src, null output), E_OVERFLOW when
+ * max_weight * n >= 0xFFFFFFFE (a tentative distance could overflow),
+ * E_UNSUPPORTED when max_weight > 2047, E_NOMEM when the bucket workspace
+ * cannot be allocated. */
+int gbgpu_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent,
+               const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
+/* Batched multi-source BFS on one graph: k independent BFS problems solved
+ * together with one 64-bit frontier mask per vertex and group of 64 sources.
+ *   srcs    host int32[k], each in [0, n) (repeats allowed)
+ *   dist    dev int32[k * n], row i = BFS from srcs[i] (same encoding as
+ *           gbgpu_bfs)
+ *   parent  dev int32[k * n], row i = min-ID parents for srcs[i]
+ * Results are identical to k calls of gbgpu_bfs.
+ * Errors: E_INVALID for k < 1, a bad source or null pointers. */
+int gbgpu_bfs_multi(gbgpu_graph g, const int32_t* srcs, int32_t k,
+                    int32_t* dist, int32_t* parent, const gbgpu_opts* o,
+                    gbgpu_stats* st, void* stream);
+
+/* Uneven batch: nq BFS queries over several graphs in one persistent launch.
+ *   graphs   host array of nq graph handles (repeats allowed, any sizes)
+ *   srcs     host int32[nq]
+ *   dists    host array of nq dev int32* outputs (each n_i long)
+ *   parents  host array of nq dev int32* outputs (each n_i long)
+ * Results are identical to gbgpu_bfs on each query. */
+int gbgpu_bfs_batch(const gbgpu_graph* graphs, const int32_t* srcs, int32_t nq,
+                    int32_t* const* dists, int32_t* const* parents,
+                    const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: resident graphs, queries admitted by device-memory footprint,   */
+/* continuous batching, per-query latency.                                  */
+/* ---------------------------------------------------------------------- */
+typedef struct gbgpu_server_s* gbgpu_server;
+
+enum { GBGPU_QUERY_BFS = 0, GBGPU_QUERY_WBFS = 1 };
+
+typedef struct {
+    int32_t graph_id; /* id from gbgpu_server_add_graph                    */
+    int32_t kind;     /* GBGPU_QUERY_BFS or GBGPU_QUERY_WBFS                */
+    int32_t src;      /* source vertex                                      */
+    int32_t reserved;
+    void* dist;       /* dev int32[n] (BFS) or uint32[n] (wBFS) output      */
+    int32_t* parent;  /* dev int32[n] output                                */
+} gbgpu_query;
+
+typedef struct {
+    int32_t status;      /* GBGPU_OK, or the query's error status          */
+    int32_t rounds;      /* rounds / buckets the query took                */
+    int64_t t_arrive_ns; /* CLOCK_MONOTONIC time of gbgpu_submit           */
+    int64_t t_start_ns;  /* time the query was admitted to the device      */
+    int64_t t_done_ns;   /* time its outputs were known complete           */
+} gbgpu_result;
+
+/* Create a server.
+ *   arena, arena_bytes  dev memory the server carves per-query workspaces
+ *                       from (caller-owned, kept alive until destroy);
+ *                       admission never exceeds it
+ *   max_inflight        queries resident on the device at once (>= 1)
+ *   o                   tuning options for every query (NULL allowed) */
+int gbgpu_server_create(void* arena, size_t arena_bytes, int32_t max_inflight,
+                        const gbgpu_opts* o, gbgpu_server* out);
+
+/* Make a loaded graph servable; returns its id.  The handle must outlive the
+ * server. */
+int gbgpu_server_add_graph(gbgpu_server sv, gbgpu_graph g, int32_t* graph_id);
+
+/* Enqueue a query (copied).  E_AGAIN when the pending queue is full,
+ * E_INVALID for a bad graph id, kind, source or output pointer, E_NOMEM when
+ * the query's footprint alone exceeds the arena. */
+int gbgpu_submit(gbgpu_server sv, const gbgpu_query* q, uint64_t* ticket);
+
+/* Result of a ticket: GBGPU_OK with *r filled once done (the ticket is then
+ * released), E_AGAIN while pending or running, E_NOTFOUND for an unknown or
+ * already-collected ticket. */
+int gbgpu_poll(gbgpu_server sv, uint64_t ticket, gbgpu_result* r);
+
+/* Block until every submitted query has finished. */
+int gbgpu_server_drain(gbgpu_server sv);
+
+/* Stop the scheduler, wait for running queries and free the server. */
+int gbgpu_server_destroy(gbgpu_server sv);
+
+/* Bytes of device workspace one query of this kind needs on this graph (what
+ * admission charges against the arena). */
+int gbgpu_query_footprint(gbgpu_graph g, int32_t kind, size_t* bytes);
+
+/* ---------------------------------------------------------------------- */
+/* Diagnostics                                                              */
+/* ---------------------------------------------------------------------- */
+/* Per-round log of the last gbgpu_bfs on g, 4 uint32 per round: direction
+ * (1 sparse push from the queue, 2 dense pull, 3 sparse push from the
+ * bitmap), |U_r|, sum of deg(U_r), whether the sparse queue was available.
+ * out holds max_rounds * 4 words (host). */
+int gbgpu_debug_bfs_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds);
+
+/* Per-bucket log of the last gbgpu_wbfs on g, 4 uint32 per bucket step:
+ * bucket (distance), entries extracted (live and stale), sum of their
+ * degrees, 0.  out holds max_steps * 4 words (host). */
+int gbgpu_debug_wbfs_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBGPU_H */

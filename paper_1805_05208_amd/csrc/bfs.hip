@@ -1,0 +1,570 @@
+// Single-source BFS: frontier rounds of edgeMap with a sparse (push) / dense
+// (pull) switch decided on the device every round.
+//
+// Method (paper: BFS algorithm box; edgeMap in Preliminaries, "Ligra, Ligra+,
+// and Julienne"; blocked sparse traversal in the "edgeMapBlocked" section):
+//   round r processes the frontier U_r (vertices at distance r) and produces
+//   U_{r+1}.  Sparse rounds walk the frontier's edges in edge-balanced blocks;
+//   dense rounds let every unvisited vertex scan its own (in-)edges in order
+//   and stop at the first frontier neighbour.  The switch goes dense when
+//   |U| + sum deg(U) exceeds m / tau.
+// Determinism: the paper's test-and-set leaves the parent to a race; here
+//   push rounds take atomicMin over frontier neighbours and dense rounds scan
+//   ascending lists and stop at the first hit, so both give
+//   parent[v] = min{u in N(v) : D[u] = D[v] - 1} and the direction schedule
+//   never changes the result.
+//
+// Device state (all words are uint32):
+//   V        visited bitmap (vertices of distance < r, plus degree-0 vertices)
+//   F[3]     frontier bitmaps; F[r%3] = U_r, F[(r+1)%3] receives U_{r+1},
+//            F[(r+2)%3] is cleared during round r for round r+1
+//   Q[2],P[2] sparse frontier: vertex ids and exclusive degree prefix sums
+//   cnt[4]   per-round totals, (|U_r| << 32) | sum deg(U_r)
+//   qcnt[4]  per-round queue reservations, same packing
+//   qover[4] 1 when round r's queue was abandoned (too large to be useful)
+// A vertex is "visited for round r" when V | F[r%3] has its bit; V is folded
+// with U_r during round r without changing that union.
+
+#include "common.h"
+#include "emit.h"
+
+namespace gb {
+
+constexpr int kLogCap = 8192;
+
+struct BfsWs {
+    int64_t n = 0;
+    int64_t nwords = 0;
+    uint32_t* V = nullptr;
+    uint32_t* F[3] = {nullptr, nullptr, nullptr};
+    uint32_t* Q[2] = {nullptr, nullptr};
+    uint32_t* P[2] = {nullptr, nullptr};
+    unsigned long long* ctl = nullptr;  // cnt[4], qcnt[4], qover[4] (as u64)
+    uint32_t* log = nullptr;            // kLogCap * 4
+    unsigned long long* host_ctl = nullptr;  // pinned readback
+    void* block = nullptr;              // single device allocation
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+void free_bfs_ws(BfsWs* w) {
+    if (!w) return;
+    if (w->block) (void)hipFree(w->block);
+    if (w->host_ctl) (void)hipHostFree(w->host_ctl);
+    if (w->ev0) (void)hipEventDestroy(w->ev0);
+    if (w->ev1) (void)hipEventDestroy(w->ev1);
+    delete w;
+}
+
+static int ensure_bfs_ws(gbgpu_graph g) {
+    if (g->bfs) return GBGPU_OK;
+    BfsWs* w = new BfsWs();
+    w->n = g->n;
+    w->nwords = g->nwords;
+    size_t bm = (size_t)g->nwords * 4;
+    size_t qv = (size_t)(g->n + 64) * 4;
+    size_t ctl = (64 + 4 * kSpread * kSpreadStride) * 8;
+    size_t lg = (size_t)kLogCap * 4 * 4;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t total = al(bm) * 4 + al(qv) * 4 + al(ctl) + al(lg);
+    hipError_t e = hipMalloc(&w->block, total);
+    if (e != hipSuccess) {
+        delete w;
+        return set_error(GBGPU_E_NOMEM, "BFS workspace of %zu bytes: %s", total,
+                         hipGetErrorString(e));
+    }
+    char* p = (char*)w->block;
+    w->V = (uint32_t*)p; p += al(bm);
+    for (int i = 0; i < 3; ++i) { w->F[i] = (uint32_t*)p; p += al(bm); }
+    for (int i = 0; i < 2; ++i) { w->Q[i] = (uint32_t*)p; p += al(qv); }
+    for (int i = 0; i < 2; ++i) { w->P[i] = (uint32_t*)p; p += al(qv); }
+    w->ctl = (unsigned long long*)p; p += al(ctl);
+    w->log = (uint32_t*)p;
+    if (hipHostMalloc((void**)&w->host_ctl, kSpread * kSpreadStride * 8, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess) {
+        free_bfs_ws(w);
+        return set_error(GBGPU_E_HIP, "BFS workspace: pinned buffer or event creation failed");
+    }
+    g->bfs = w;
+    return GBGPU_OK;
+}
+
+struct BfsArgs {
+    const int64_t* off;
+    const int32_t* nbr;
+    const uint32_t* deg;
+    uint32_t* V;
+    uint32_t* F0;
+    uint32_t* F1;
+    uint32_t* F2;
+    uint32_t* Q0;
+    uint32_t* Q1;
+    uint32_t* P0;
+    uint32_t* P1;
+    int32_t* dist;
+    uint32_t* parent;
+    unsigned long long* ctl;
+    uint32_t* log;
+    int64_t n;
+    int64_t nwords;
+    uint64_t dense_thresh;  // go dense when |U| + sum deg(U) > dense_thresh
+    int32_t force_dir;
+    int32_t light;
+    uint32_t chunk_cap;
+};
+
+// ---------------------------------------------------------------------------
+// init: dist = INF, parent = -1, V = zero-degree mask, F = {src}, Q = [src]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint32_t* zmask,
+                                                          uint32_t src) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = tid; v < a.n; v += stride) {
+        a.dist[v] = v == src ? 0 : INT32_MAX;
+        a.parent[v] = v == src ? src : kNone;
+    }
+    for (int64_t w = tid; w < a.nwords; w += stride) {
+        a.V[w] = zmask[w];
+        a.F0[w] = (w == (int64_t)(src >> 5)) ? (1u << (src & 31)) : 0u;
+        a.F1[w] = 0u;
+        a.F2[w] = 0u;
+    }
+    if (tid == 0) {
+        a.Q0[0] = src;
+        a.P0[0] = 0;
+        unsigned long long* qcnt = a.ctl + 4;
+        unsigned long long* qover = a.ctl + 8;
+        const uint32_t src_deg = a.deg[src];
+        qcnt[0] = (1ull << 32) | src_deg;
+        for (int i = 1; i < 4; ++i) qcnt[i] = 0;
+        for (int i = 0; i < 4; ++i) qover[i] = 0;
+    }
+    // round totals: 4 slots of kSpread counters; slot 0 holds U_0 = {src}
+    unsigned long long* tot = a.ctl + 64;
+    for (int64_t i = tid; i < 4 * kSpread; i += stride)
+        tot[i * kSpreadStride] = i == 0 ? ((1ull << 32) | a.deg[src]) : 0ull;
+}
+
+// Sparse-round edge operation: claim v for round r+1 with the smallest
+// frontier neighbour as parent (check-before-atomic, then atomicMin).
+struct PushPolicy {
+    const BfsArgs* a;
+    const uint32_t* Fc;
+    uint32_t* Fn;
+    WgQueue* q;
+    const QueueOut* out;
+    uint32_t r;
+    static constexpr bool kSkipDead = false;
+
+    __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
+
+    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e) {
+        bool claim = false;
+        uint32_t v = 0, dv = 0;
+        if (act) {
+            v = (uint32_t)a->nbr[e];
+            const uint32_t w = v >> 5, bit = 1u << (v & 31);
+            if (!((a->V[w] | Fc[w]) & bit)) {
+                uint32_t pv = a->parent[v];
+                if (u < pv) {
+                    uint32_t old = atomicMin(&a->parent[v], u);
+                    if (old == kNone) {
+                        claim = true;
+                        a->dist[v] = (int32_t)(r + 1);
+                        atomicOr(&Fn[w], bit);
+                        dv = a->deg[v];
+                    }
+                }
+            }
+        }
+        wgq_push(*q, claim, v, dv, *out);
+    }
+
+    __device__ __forceinline__ void window_done() {}
+};
+
+__device__ __forceinline__ bool choose_push(const BfsArgs& a, uint32_t r, uint32_t count,
+                                            uint32_t edges) {
+    if (a.force_dir == 1) return true;
+    if (a.force_dir == 2) return false;
+    if (a.force_dir == 3) return (r & 1u) == 0u;
+    return (uint64_t)count + edges <= a.dense_thresh;
+}
+
+// Dense (pull) processing of kPullG consecutive groups of 64 vertices by one
+// wavefront; lane l owns vertex 64*(g0+j)+l of each group j.  Each unvisited
+// vertex scans its list in ascending order and stops at the first member of
+// the frontier, which is its parent.  The groups are processed together so
+// that every lane keeps up to kPullG * 4 independent loads in flight.
+constexpr int kPullG = 2;
+
+__device__ __forceinline__ void pull_groups(const BfsArgs& a, uint32_t r, int64_t g0,
+                                            const uint32_t* __restrict__ Fc, uint32_t* Fn,
+                                            uint32_t* Fclr, uint32_t& found, uint32_t& dsum) {
+    const int l = lane_id();
+    const int64_t ngroups = a.nwords / 2;
+    uint32_t vw[kPullG];
+    bool unvis[kPullG];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < kPullG; ++j) {
+        const int64_t w = 2 * (g0 + j) + (l >> 5);
+        vw[j] = (g0 + j < ngroups) ? (a.V[w] | Fc[w]) : ~0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPullG; ++j) {
+        const int64_t w = 2 * (g0 + j) + (l >> 5);
+        const int64_t v = 64 * (g0 + j) + l;
+        if (g0 + j < ngroups && (l & 31) == 0) {
+            a.V[w] = vw[j];
+            Fclr[w] = 0u;
+        }
+        unvis[j] = v < a.n && !((vw[j] >> (l & 31)) & 1u);
+        any |= unvis[j];
+    }
+    if (ballot(any) == 0) {
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j)
+            if (g0 + j < ngroups && (l & 31) == 0) Fn[2 * (g0 + j) + (l >> 5)] = 0u;
+        return;
+    }
+    int64_t s[kPullG], e[kPullG], k[kPullG], lim[kPullG];
+    uint32_t hit[kPullG];
+#pragma unroll
+    for (int j = 0; j < kPullG; ++j) {
+        const uint32_t v = (uint32_t)(64 * (g0 + j) + l);
+        s[j] = unvis[j] ? a.off[v] : 0;
+        e[j] = unvis[j] ? a.off[v + 1] : 0;
+        lim[j] = min(e[j], s[j] + (int64_t)a.light);
+        k[j] = s[j];
+        hit[j] = kNone;
+    }
+    // light phase: lanes scan up to `light` neighbours of each of their
+    // vertices, four at a time, in ascending order
+    for (;;) {
+        bool act[kPullG];
+        bool any_act = false;
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j) {
+            act[j] = k[j] < lim[j] && hit[j] == kNone;
+            any_act |= act[j];
+        }
+        if (!any_act) break;
+        uint32_t u[kPullG][4];
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                u[j][i] = (act[j] && k[j] + i < lim[j]) ? (uint32_t)a.nbr[k[j] + i] : kNone;
+        bool h[kPullG][4];
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[j][i] = u[j][i] != kNone && test_bit(Fc, u[j][i]);
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j) {
+            if (act[j]) {
+                hit[j] = h[j][0] ? u[j][0] : h[j][1] ? u[j][1] : h[j][2] ? u[j][2]
+                       : h[j][3] ? u[j][3] : kNone;
+                k[j] += 4;
+            }
+        }
+    }
+    // heavy phase: vertices with neighbours left are scanned by the whole
+    // wavefront, 128 neighbours per step, first hit wins
+#pragma unroll
+    for (int j = 0; j < kPullG; ++j) {
+        uint64_t hm = ballot(unvis[j] && hit[j] == kNone && lim[j] < e[j]);
+        while (hm) {
+            const int hl = first_lane(hm);
+            hm &= hm - 1;
+            const int64_t hs = (int64_t)shfl64((uint64_t)lim[j], hl);
+            const int64_t he = (int64_t)shfl64((uint64_t)e[j], hl);
+            uint32_t fu = kNone;
+            for (int64_t b = hs; b < he; b += 128) {
+                const int64_t i0 = b + l, i1 = b + 64 + l;
+                const uint32_t u0 = i0 < he ? (uint32_t)a.nbr[i0] : 0u;
+                const uint32_t u1 = i1 < he ? (uint32_t)a.nbr[i1] : 0u;
+                const bool h0 = i0 < he && test_bit(Fc, u0);
+                const bool h1 = i1 < he && test_bit(Fc, u1);
+                const uint64_t b0 = ballot(h0);
+                if (b0) {
+                    fu = __shfl(u0, first_lane(b0), 64);
+                    break;
+                }
+                const uint64_t b1 = ballot(h1);
+                if (b1) {
+                    fu = __shfl(u1, first_lane(b1), 64);
+                    break;
+                }
+            }
+            if (l == hl) hit[j] = fu;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kPullG; ++j) {
+        const bool got = hit[j] != kNone;
+        if (got) {
+            const uint32_t v = (uint32_t)(64 * (g0 + j) + l);
+            a.dist[v] = (int32_t)(r + 1);
+            a.parent[v] = hit[j];
+            found += 1;
+            dsum += (uint32_t)(e[j] - s[j]);
+        }
+        const uint64_t fm = ballot(got);
+        if (g0 + j < ngroups) {
+            const int64_t w = 2 * (g0 + j);
+            if (l == 0) Fn[w] = (uint32_t)fm;
+            if (l == 32) Fn[w + 1] = (uint32_t)(fm >> 32);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32_t r) {
+    __shared__ WgQueue q;
+    __shared__ unsigned long long s_tot;
+
+    unsigned long long* qcnt = a.ctl + 4;
+    unsigned long long* qover = a.ctl + 8;
+    unsigned long long* tot = a.ctl + 64;  // 4 slots x kSpread x kSpreadStride
+    const uint32_t rs = r & 3u;
+    if (threadIdx.x < kWave) {
+        const unsigned long long t = spread_sum(tot + (size_t)rs * kSpread * kSpreadStride);
+        if (threadIdx.x == 0) s_tot = t;
+    }
+    wgq_init(q);
+    __syncthreads();
+    const unsigned long long packed = s_tot;
+    const uint32_t r2 = (r + 2) & 3u;
+    if (blockIdx.x == 0 && threadIdx.x < kSpread) {
+        // slots of round r+2 are unused during round r; cleared
+        // unconditionally so rounds past the end read an empty frontier
+        tot[((size_t)r2 * kSpread + threadIdx.x) * kSpreadStride] = 0ull;
+        if (threadIdx.x == 0) {
+            qcnt[r2] = 0;
+            qover[r2] = 0;
+        }
+    }
+    const uint32_t count = (uint32_t)(packed >> 32);
+    const uint32_t edges = (uint32_t)packed;
+    if (count == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && r < (uint32_t)kLogCap) a.log[4 * r + 1] = 0u;
+        return;
+    }
+    const bool qvalid = qover[rs] == 0;
+    const bool push = choose_push(a, r, count, edges);
+
+    uint32_t* Fs[3] = {a.F0, a.F1, a.F2};
+    const uint32_t* Fc = Fs[r % 3];
+    uint32_t* Fn = Fs[(r + 1) % 3];
+    uint32_t* Fclr = Fs[(r + 2) % 3];
+    const uint32_t* Qc = (r & 1) ? a.Q1 : a.Q0;
+    const uint32_t* Pc = (r & 1) ? a.P1 : a.P0;
+
+    const int l = lane_id();
+    const int wib = threadIdx.x / kWave;
+    const uint32_t gwave = blockIdx.x * kRWaves + wib;
+    const uint32_t nwaves = gridDim.x * kRWaves;
+    const uint32_t r1 = (r + 1) & 3u;
+    QueueOut out;
+    out.Q = (r & 1) ? a.Q0 : a.Q1;
+    out.P = (r & 1) ? a.P0 : a.P1;
+    out.qcnt = &qcnt[r1];
+    out.qover = &qover[r1];
+    out.qlimit = (a.force_dir == 1 || a.force_dir == 3) ? ~0ull : a.dense_thresh;
+    out.tot = tot + (size_t)r1 * kSpread * kSpreadStride;
+
+    if (blockIdx.x == 0 && threadIdx.x == 0 && r < (uint32_t)kLogCap) {
+        a.log[4 * r + 0] = push ? (qvalid ? 1u : 3u) : 2u;
+        a.log[4 * r + 1] = count;
+        a.log[4 * r + 2] = edges;
+        a.log[4 * r + 3] = qvalid ? 1u : 0u;
+    }
+
+    if (push) {
+        // clear the bitmap that round r+1 writes
+        for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwords;
+             w += (int64_t)gridDim.x * blockDim.x)
+            Fclr[w] = 0u;
+        PushPolicy pol{&a, Fc, Fn, &q, &out, r};
+        if (qvalid) {
+            // sparse frontier: fold U_r into V (leaves V | F_r unchanged),
+            // then walk its edges in edge-balanced chunks
+            for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
+                 i += gridDim.x * blockDim.x) {
+                uint32_t u = Qc[i];
+                atomicOr(&a.V[u >> 5], 1u << (u & 31));
+            }
+            const uint32_t wc = wave_chunk(edges, nwaves, a.chunk_cap);
+            const uint32_t nchunks = (edges + wc - 1) / wc;
+            for (uint32_t c = gwave; c < nchunks; c += nwaves) {
+                const uint32_t eb = c * wc;
+                expand_range(Qc, Pc, count, edges, a.off, eb, min(edges, eb + wc), pol);
+            }
+        } else {
+            // the frontier exists only as a bitmap (after a dense round):
+            // each wavefront converts 64 words at a time to vertex ids with a
+            // popcount prefix and expands them 64 at a time
+            // wavefront gwave takes words gwave + nwaves * (64 * it + lane), so
+            // a frontier clustered in one id range is spread over all waves
+            const int64_t span = (int64_t)nwaves * 64;
+            const int64_t nit = (a.nwords + span - 1) / span;
+            for (int64_t it = 0; it < nit; ++it) {
+                const int64_t w = gwave + (int64_t)nwaves * (64 * it + l);
+                const uint32_t fw = w < a.nwords ? Fc[w] : 0u;
+                if (fw) a.V[w] |= fw;
+                const uint32_t c = (uint32_t)__popc(fw);
+                const uint32_t inc = wave_incl_sum(c);
+                const uint32_t total = __shfl(inc, 63, 64);
+                const uint32_t excl = inc - c;
+                for (uint32_t B = 0; B < total; B += 64) {
+                    const uint32_t j = B + (uint32_t)l;
+                    const bool valid = j < total;
+                    int o = 0;
+#pragma unroll
+                    for (int s = 32; s >= 1; s >>= 1) {
+                        uint32_t pv = __shfl(excl, o + s, 64);
+                        if (pv <= j) o += s;
+                    }
+                    const uint32_t fo = __shfl(fw, o, 64);
+                    const uint32_t k = j - __shfl(excl, o, 64);
+                    uint32_t u = 0, dg = 0;
+                    int64_t st = 0;
+                    if (valid) {
+                        const int64_t wo = gwave + (int64_t)nwaves * (64 * it + o);
+                        u = (uint32_t)(wo * 32) + select_bit(fo, k);
+                        st = a.off[u];
+                        dg = a.deg[u];
+                    }
+                    expand_lanes(valid, u, st, dg, pol);
+                }
+            }
+        }
+        wgq_finish(q, out, true);
+    } else {
+        // dense round: each wavefront owns groups of 64 consecutive vertices;
+        // the output is the bitmap only
+        if (blockIdx.x == 0 && threadIdx.x == 0) *out.qover = 1ull;
+        uint32_t found = 0, dsum = 0;
+        const int64_t ngroups = a.nwords / 2;
+        const int64_t nquads = (ngroups + kPullG - 1) / kPullG;
+        for (int64_t qi = gwave; qi < nquads; qi += nwaves)
+            pull_groups(a, r, qi * kPullG, Fc, Fn, Fclr, found, dsum);
+        found = wave_sum(found);
+        dsum = wave_sum(dsum);
+        if (l == 0 && found) {
+            atomicAdd(&q.found, found);
+            atomicAdd(&q.fdsum, dsum);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && q.found)
+            atomicAdd(&out.tot[(blockIdx.x % kSpread) * kSpreadStride],
+                      ((unsigned long long)q.found << 32) | q.fdsum);
+    }
+}
+
+int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+            const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream) {
+    const double t0 = now_ms();
+    GB_TRY(ensure_bfs_ws(g));
+    BfsWs* w = g->bfs;
+    BfsArgs a;
+    a.off = g->off;
+    a.nbr = g->nbr;
+    a.deg = g->deg;
+    a.V = w->V;
+    a.F0 = w->F[0];
+    a.F1 = w->F[1];
+    a.F2 = w->F[2];
+    a.Q0 = w->Q[0];
+    a.Q1 = w->Q[1];
+    a.P0 = w->P[0];
+    a.P1 = w->P[1];
+    a.dist = dist;
+    a.parent = (uint32_t*)parent;
+    a.ctl = w->ctl;
+    a.log = w->log;
+    a.n = g->n;
+    a.nwords = g->nwords;
+    a.dense_thresh = (uint64_t)g->m / (uint64_t)o.tau;
+    a.force_dir = o.force_direction;
+    a.light = o.pull_light;
+    a.chunk_cap = (uint32_t)o.wave_chunk;
+
+    const int64_t work = std::max<int64_t>(g->nwords / 32, g->m / 4096);
+    int grid = (int)std::min<int64_t>(std::max<int64_t>(work, 1), o.grid);
+    int igrid = (int)std::min<int64_t>((g->n + kBlock - 1) / kBlock, 4096);
+    if (igrid < 1) igrid = 1;
+    hipLaunchKernelGGL(bfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, g->zmask,
+                       (uint32_t)src);
+    GB_HIP(hipGetLastError());
+
+    int launches = 0;
+    double kms = 0.0;
+    uint32_t r = 0;
+    int K = o.rounds_per_sync;
+    const uint32_t max_rounds = (uint32_t)std::min<int64_t>(g->n + 2, 0x7FFFFFFF);
+    for (;;) {
+        if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
+        for (int i = 0; i < K; ++i) {
+            hipLaunchKernelGGL(bfs_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, a, r + i);
+        }
+        GB_HIP(hipGetLastError());
+        if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
+        launches += K;
+        r += (uint32_t)K;
+        GB_HIP(hipMemcpyAsync(w->host_ctl, w->ctl + 64 + (size_t)(r & 3u) * kSpread * kSpreadStride,
+                              kSpread * kSpreadStride * 8, hipMemcpyDeviceToHost, stream));
+        GB_HIP(hipStreamSynchronize(stream));
+        if (o.profile) {
+            float ms = 0.f;
+            GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+            kms += ms;
+        }
+        unsigned long long t = 0;
+        for (int i = 0; i < kSpread; ++i) t += w->host_ctl[i * kSpreadStride];
+        if ((t >> 32) == 0) break;
+        if (r > max_rounds)
+            return set_error(GBGPU_E_HIP, "BFS did not terminate within n rounds");
+        K = std::min(K * 2, 512);
+    }
+    if (st) {
+        std::vector<uint32_t> lg((size_t)std::min<uint32_t>(r, (uint32_t)kLogCap) * 4);
+        if (!lg.empty()) {
+            GB_HIP(hipMemcpyAsync(lg.data(), w->log, lg.size() * 4, hipMemcpyDeviceToHost, stream));
+            GB_HIP(hipStreamSynchronize(stream));
+        }
+        memset(st, 0, sizeof(*st));
+        int64_t reached = 0, ex = 0;
+        for (size_t i = 0; i < lg.size() / 4; ++i) {
+            if (lg[4 * i + 1] == 0) break;
+            st->rounds++;
+            if (lg[4 * i] == 2) st->pull_rounds++; else st->push_rounds++;
+            reached += lg[4 * i + 1];
+            ex += lg[4 * i + 2];
+        }
+        st->reached = reached;
+        st->edges_examined = ex;
+        st->launches = launches;
+        st->kernel_ms = kms;
+        st->wall_ms = now_ms() - t0;
+    }
+    return GBGPU_OK;
+}
+
+// Round log of the last BFS on this graph: 4 words per round (direction 1 =
+// sparse / 2 = dense, |U_r|, sum deg(U_r), queue valid).  Used by tests and
+// the benchmark's byte model.
+int bfs_round_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds) {
+    if (!g->bfs) { *nrounds = 0; return GBGPU_OK; }
+    int32_t k = std::min<int32_t>(max_rounds, kLogCap);
+    std::vector<uint32_t> lg((size_t)k * 4);
+    GB_HIP(hipMemcpy(lg.data(), g->bfs->log, lg.size() * 4, hipMemcpyDeviceToHost));
+    int32_t r = 0;
+    while (r < k && lg[4 * r + 1] != 0) ++r;
+    memcpy(out, lg.data(), (size_t)r * 16);
+    *nrounds = r;
+    return GBGPU_OK;
+}
+
+}  // namespace gb

@@ -1,0 +1,313 @@
+// Graph handles, load-time validation, options, errors, and the C entry
+// points for single-source traversal.
+//
+// The CSR layout (Preliminaries, "Graph Notation": vertices 0..n-1, no self
+// edges or duplicates; CSR/CSC formats) is used as given: int64 offsets,
+// int32 neighbours sorted ascending, optional int32 weights aligned with the
+// neighbours.  Graphs are symmetric, so a vertex's list serves as both its
+// out-edges (sparse push) and in-edges (dense pull).
+
+#include <time.h>
+
+#include "common.h"
+
+namespace gb {
+
+static thread_local std::string t_last_error;
+
+int set_error(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    return status;
+}
+
+double now_ms() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return ts.tv_sec * 1e3 + ts.tv_nsec * 1e-6;
+}
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
+}
+
+gbgpu_opts resolve_opts(const gbgpu_opts* o) {
+    gbgpu_opts r;
+    memset(&r, 0, sizeof(r));
+    if (o) r = *o;
+    if (r.force_direction < 0 || r.force_direction > 3) r.force_direction = 0;
+    if (r.tau <= 0) r.tau = 20;
+    if (r.pull_light <= 0) r.pull_light = 32;
+    if (r.wave_chunk <= 0) r.wave_chunk = 256;
+    r.wave_chunk = std::max(64, (r.wave_chunk + 63) & ~63);
+    if (r.grid <= 0) r.grid = 512;
+    if (r.rounds_per_sync <= 0) r.rounds_per_sync = 12;
+    if (r.bucket_window < 0) r.bucket_window = 0;
+    if (r.bucket_capacity < 0) r.bucket_capacity = 0;
+    return r;
+}
+
+int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
+            gbgpu_stats* st, hipStream_t stream);
+int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts& o,
+             gbgpu_stats* st, hipStream_t stream);
+int bfs_round_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds);
+int wbfs_step_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps);
+
+// ---------------------------------------------------------------------------
+// load-time kernels
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+    VF_OFFSETS = 1u,
+    VF_RANGE = 2u,
+    VF_ORDER = 4u,
+    VF_SELF = 8u,
+    VF_ASYM = 16u,
+    VF_WEIGHT = 32u,
+    VF_WASYM = 64u,
+};
+
+__global__ void check_offsets_kernel(const int64_t* off, int64_t n, int64_t m, uint32_t* flag) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; v < n; v += stride) {
+        int64_t a = off[v], b = off[v + 1];
+        if (a > b || a < 0 || b > m) atomicOr(flag, VF_OFFSETS);
+        if (v == 0 && a != 0) atomicOr(flag, VF_OFFSETS);
+        if (v == n - 1 && b != m) atomicOr(flag, VF_OFFSETS);
+    }
+}
+
+// Binary search for x in the sorted list of vertex v; returns its edge index
+// or -1.
+__device__ int64_t find_in_list(const int64_t* off, const int32_t* nbr, int64_t v, int32_t x) {
+    int64_t lo = off[v], hi = off[v + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        int32_t y = nbr[mid];
+        if (y == x) return mid;
+        if (y < x) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+__global__ void check_edges_kernel(const int64_t* off, const int32_t* nbr, const int32_t* w,
+                                   int64_t n, uint32_t* flag, int32_t* maxw) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; u < n; u += stride) {
+        int32_t prev = -1;
+        int32_t lmax = 0;
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            int32_t v = nbr[e];
+            if (v < 0 || v >= n) { atomicOr(flag, VF_RANGE); continue; }
+            if (v <= prev) atomicOr(flag, VF_ORDER);
+            prev = v;
+            if (v == u) atomicOr(flag, VF_SELF);
+            int64_t back = find_in_list(off, nbr, v, (int32_t)u);
+            if (back < 0) atomicOr(flag, VF_ASYM);
+            if (w) {
+                if (w[e] < 1) atomicOr(flag, VF_WEIGHT);
+                if (back >= 0 && w[back] != w[e]) atomicOr(flag, VF_WASYM);
+                lmax = max(lmax, w[e]);
+            }
+        }
+        if (w && lmax > 0) atomicMax(maxw, lmax);
+    }
+}
+
+__global__ void max_weight_kernel(const int32_t* w, int64_t m, int32_t* maxw) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t lm = 0;
+    for (; e < m; e += stride) lm = max(lm, w[e]);
+    for (int d = 32; d >= 1; d >>= 1) lm = max(lm, __shfl_xor(lm, d, 64));
+    if (lane_id() == 0 && lm > 0) atomicMax(maxw, lm);
+}
+
+__global__ void degree_kernel(const int64_t* off, int64_t n, int64_t nwords, uint32_t* deg,
+                              uint32_t* zmask) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = t; v < n; v += stride) deg[v] = (uint32_t)(off[v + 1] - off[v]);
+    for (int64_t w = t; w < nwords; w += stride) {
+        uint32_t bits = 0;
+        for (int b = 0; b < 32; ++b) {
+            int64_t v = w * 32 + b;
+            if (v >= n || off[v + 1] == off[v]) bits |= 1u << b;
+        }
+        zmask[w] = bits;
+    }
+}
+
+static int grid_for(int64_t items) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+}  // namespace gb
+
+using namespace gb;
+
+extern "C" {
+
+const char* gbgpu_last_error(void) { return t_last_error.c_str(); }
+
+int gbgpu_version(void) { return 10000; }
+
+int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* neighbors,
+                   const int32_t* weights, uint32_t flags, void* stream, gbgpu_graph* out) {
+    if (!out) return set_error(GBGPU_E_INVALID, "out is NULL");
+    if (!offsets) return set_error(GBGPU_E_INVALID, "offsets is NULL");
+    if (m > 0 && !neighbors) return set_error(GBGPU_E_INVALID, "neighbors is NULL");
+    if (n <= 0) return set_error(GBGPU_E_INVALID, "n must be positive (got %lld)", (long long)n);
+    if (m < 0) return set_error(GBGPU_E_INVALID, "m must be non-negative");
+    if (n >= (1ll << 31) - 1)
+        return set_error(GBGPU_E_UNSUPPORTED, "n = %lld exceeds 2^31 - 2", (long long)n);
+    if (m >= (1ll << 32))
+        return set_error(GBGPU_E_UNSUPPORTED, "m = %lld exceeds 2^32 - 1", (long long)m);
+    if (!(flags & GBGPU_SYMMETRIC))
+        return set_error(GBGPU_E_INVALID,
+                         "GBGPU_SYMMETRIC is required: dense rounds read a vertex's own list "
+                         "as its in-edges");
+    hipStream_t s = (hipStream_t)stream;
+    gbgpu_graph g = new gbgpu_graph_s();
+    g->n = n;
+    g->m = m;
+    g->off = offsets;
+    g->nbr = neighbors;
+    g->w = weights;
+    g->nwords = ((n + 63) / 64) * 2;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { delete g; return set_error(GBGPU_E_HIP, "hipGetDevice failed"); }
+    g->device = dev;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        g->num_cus = cus;
+    uint32_t* scratch = nullptr;  // [0] flag, [1] max weight
+    auto fail = [&](int st) {
+        if (g->deg) (void)hipFree(g->deg);
+        if (g->zmask) (void)hipFree(g->zmask);
+        if (scratch) (void)hipFree(scratch);
+        delete g;
+        return st;
+    };
+    if (hipMalloc(&g->deg, (size_t)n * 4) != hipSuccess ||
+        hipMalloc(&g->zmask, (size_t)g->nwords * 4) != hipSuccess ||
+        hipMalloc(&scratch, 16) != hipSuccess)
+        return fail(set_error(GBGPU_E_NOMEM, "graph metadata allocation failed"));
+    if (hipMemsetAsync(scratch, 0, 16, s) != hipSuccess)
+        return fail(set_error(GBGPU_E_HIP, "hipMemsetAsync failed"));
+    uint32_t host[4] = {0, 0, 0, 0};
+    if (flags & GBGPU_VALIDATE) {
+        hipLaunchKernelGGL(check_offsets_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, offsets, n,
+                           m, scratch);
+        if (hipMemcpyAsync(host, scratch, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(set_error(GBGPU_E_HIP, "offset validation failed to run"));
+        if (host[0]) return fail(set_error(GBGPU_E_INVALID, "invalid offsets (non-monotone, "
+                                           "offsets[0] != 0 or offsets[n] != m)"));
+        if (m > 0) {
+            hipLaunchKernelGGL(check_edges_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, offsets,
+                               neighbors, weights, n, scratch, (int32_t*)(scratch + 1));
+            if (hipMemcpyAsync(host, scratch, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(set_error(GBGPU_E_HIP, "edge validation failed to run"));
+            uint32_t f = host[0];
+            if (f & VF_RANGE) return fail(set_error(GBGPU_E_INVALID, "neighbour id out of range"));
+            if (f & VF_ORDER)
+                return fail(set_error(GBGPU_E_INVALID, "adjacency list not strictly ascending"));
+            if (f & VF_SELF) return fail(set_error(GBGPU_E_INVALID, "self loop"));
+            if (f & VF_ASYM) return fail(set_error(GBGPU_E_INVALID, "graph is not symmetric"));
+            if (f & VF_WEIGHT) return fail(set_error(GBGPU_E_INVALID, "weight < 1"));
+            if (f & VF_WASYM) return fail(set_error(GBGPU_E_INVALID, "weights are not symmetric"));
+        }
+    } else if (weights && m > 0) {
+        hipLaunchKernelGGL(max_weight_kernel, dim3(grid_for(m)), dim3(kBlock), 0, s, weights, m,
+                           (int32_t*)(scratch + 1));
+        if (hipMemcpyAsync(host, scratch, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(set_error(GBGPU_E_HIP, "max weight kernel failed"));
+    }
+    g->maxw = weights ? (int32_t)host[1] : 0;
+    if (weights && m > 0 && g->maxw < 1) return fail(set_error(GBGPU_E_INVALID, "weight < 1"));
+    hipLaunchKernelGGL(degree_kernel, dim3(grid_for(std::max<int64_t>(n, g->nwords))), dim3(kBlock),
+                       0, s, offsets, n, g->nwords, g->deg, g->zmask);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail(set_error(GBGPU_E_HIP, "degree kernel failed"));
+    (void)hipFree(scratch);
+    scratch = nullptr;
+    *out = g;
+    return GBGPU_OK;
+}
+
+int gbgpu_graph_free(gbgpu_graph g) {
+    if (!g) return set_error(GBGPU_E_INVALID, "graph is NULL");
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        free_bfs_ws(g->bfs);
+        free_wbfs_ws(g->wbfs);
+        free_multi_ws(g->multi);
+        (void)hipFree(g->deg);
+        (void)hipFree(g->zmask);
+    }
+    delete g;
+    return GBGPU_OK;
+}
+
+int gbgpu_graph_info(gbgpu_graph g, int64_t* n, int64_t* m, int32_t* max_weight) {
+    if (!g) return set_error(GBGPU_E_INVALID, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_weight) *max_weight = g->maxw;
+    return GBGPU_OK;
+}
+
+int gbgpu_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts* o,
+              gbgpu_stats* st, void* stream) {
+    if (!g) return set_error(GBGPU_E_INVALID, "graph is NULL");
+    if (!dist || !parent) return set_error(GBGPU_E_INVALID, "dist/parent is NULL");
+    if (src < 0 || src >= g->n)
+        return set_error(GBGPU_E_INVALID, "src %d out of range [0, %lld)", src, (long long)g->n);
+    gbgpu_opts opt = resolve_opts(o);
+    std::lock_guard<std::mutex> lk(g->mu);
+    return run_bfs(g, src, dist, parent, opt, st, (hipStream_t)stream);
+}
+
+int gbgpu_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts* o,
+               gbgpu_stats* st, void* stream) {
+    if (!g) return set_error(GBGPU_E_INVALID, "graph is NULL");
+    if (!g->w) return set_error(GBGPU_E_INVALID, "graph was loaded without weights");
+    if (!dist || !parent) return set_error(GBGPU_E_INVALID, "dist/parent is NULL");
+    if (src < 0 || src >= g->n)
+        return set_error(GBGPU_E_INVALID, "src %d out of range [0, %lld)", src, (long long)g->n);
+    if (g->maxw > 2047)
+        return set_error(GBGPU_E_UNSUPPORTED, "max weight %d exceeds 2047", g->maxw);
+    if ((uint64_t)std::max(g->maxw, 1) * (uint64_t)g->n >= 0xFFFFFFFEull)
+        return set_error(GBGPU_E_OVERFLOW, "max_weight * n must stay below 2^32 - 2");
+    gbgpu_opts opt = resolve_opts(o);
+    std::lock_guard<std::mutex> lk(g->mu);
+    return run_wbfs(g, src, dist, parent, opt, st, (hipStream_t)stream);
+}
+
+// Diagnostic: per-round log of the last BFS on g (4 words per round).
+int gbgpu_debug_bfs_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds) {
+    if (!g || !out || !nrounds) return set_error(GBGPU_E_INVALID, "bad argument");
+    std::lock_guard<std::mutex> lk(g->mu);
+    return bfs_round_log(g, out, max_rounds, nrounds);
+}
+
+// Diagnostic: per-step log of the last wBFS on g (4 words per bucket step).
+int gbgpu_debug_wbfs_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps) {
+    if (!g || !out || !nsteps) return set_error(GBGPU_E_INVALID, "bad argument");
+    std::lock_guard<std::mutex> lk(g->mu);
+    return wbfs_step_log(g, out, max_steps, nsteps);
+}
+
+}  // extern "C"

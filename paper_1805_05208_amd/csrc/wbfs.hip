@@ -1,0 +1,577 @@
+// Integral-weight SSSP (weighted BFS) with distance buckets.
+//
+// Method (paper: wBFS algorithm box, after Julienne): buckets hold vertices
+// by tentative distance; nextBucket returns the smallest non-empty bucket b;
+// edgeMapData relaxes the edges of bucket b's vertices with a priority-write
+// (writeMin) of the new distance; vertices whose distance dropped are moved to
+// their new bucket (vertexMap Reset + updateBuckets).  Because weights are at
+// least 1, every vertex in bucket b is settled when b is extracted, so each
+// vertex's edges are relaxed exactly once (O(m) work).
+//
+// GPU form:
+//   key[v]   uint64 = (distance << 32) | parent.  One 64-bit atomicMin is the
+//            priority-write; it also keeps the smallest parent among the
+//            neighbours that reach v at its final distance, so
+//            parent[v] = min{u in N(v) : D[u] + w(u,v) = D[v]} without a
+//            separate pass.
+//   buckets  a ring of NB slots (NB a power of two, NB >= 2*maxw + 1), slot
+//            b mod NB holding bucket b.  Pending distances lie in
+//            (b, b + maxw] while bucket b is processed, so the ring never
+//            wraps onto a live bucket, and the slot of the previous bucket can
+//            be reset by the next step without racing its writers.
+//            Each slot stores vertex ids Q and the exclusive prefix sum P of
+//            their degrees (for edge-balanced expansion) behind one packed
+//            counter (count << 32 | sum of degrees).
+//   moves    a relaxation that lowers D[v] appends v to the bucket of the new
+//            distance; an entry whose vertex has since moved lower is stale
+//            and is skipped when its bucket is extracted (GetBucketNum reads
+//            the current distance).  So updateBuckets is fused into the
+//            relaxation and each (vertex, distance) pair is appended at most
+//            once.
+//   steps    one kernel launch per bucket: the launch finds b itself (the
+//            smallest non-empty slot after the previous bucket), resets the
+//            previous slot, and relaxes bucket b.  The host only checks a done
+//            flag every few hundred launches.
+
+#include "common.h"
+#include "emit.h"
+
+namespace gb {
+
+constexpr int kWLogCap = 16384;
+constexpr uint32_t kStart = 0xFFFFFFFFu;  // "bucket before 0"
+constexpr uint32_t kDone = 0xFFFFFFFEu;
+
+struct WbfsWs {
+    int64_t n = 0;
+    uint32_t NB = 0;
+    uint32_t C = 0;
+    unsigned long long* key = nullptr;
+    uint32_t* Qs = nullptr;
+    uint32_t* Ps = nullptr;
+    unsigned long long* sc = nullptr;
+    uint32_t* ctl = nullptr;   // [0..1] bucket of step j (j & 1), [2] done, [3] overflow
+    uint32_t* log = nullptr;   // kWLogCap * 4
+    uint32_t* host_ctl = nullptr;
+    void* block = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+void free_wbfs_ws(WbfsWs* w) {
+    if (!w) return;
+    if (w->block) (void)hipFree(w->block);
+    if (w->host_ctl) (void)hipHostFree(w->host_ctl);
+    if (w->ev0) (void)hipEventDestroy(w->ev0);
+    if (w->ev1) (void)hipEventDestroy(w->ev1);
+    delete w;
+}
+
+static uint32_t window_for(int32_t maxw, int32_t req) {
+    uint32_t need = 2u * (uint32_t)std::max(maxw, 1) + 1u;
+    uint32_t nb = 2;
+    while (nb < need) nb <<= 1;
+    if (req > 0) {
+        uint32_t r = 2;
+        while (r < (uint32_t)req) r <<= 1;
+        nb = std::max(nb, r);
+    }
+    return nb;
+}
+
+size_t wbfs_bytes(int64_t n, uint32_t NB, uint32_t C) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return al((size_t)n * 8) + 2 * al((size_t)NB * C * 4) + al((size_t)NB * 8 * kSpreadStride) + al(64) +
+           al((size_t)kWLogCap * 16);
+}
+
+static int ensure_wbfs_ws(gbgpu_graph g, uint32_t NB, uint32_t C) {
+    if (g->wbfs && g->wbfs->NB == NB && g->wbfs->C == C) return GBGPU_OK;
+    free_wbfs_ws(g->wbfs);
+    g->wbfs = nullptr;
+    WbfsWs* w = new WbfsWs();
+    w->n = g->n;
+    w->NB = NB;
+    w->C = C;
+    w->bytes = wbfs_bytes(g->n, NB, C);
+    hipError_t e = hipMalloc(&w->block, w->bytes);
+    if (e != hipSuccess) {
+        size_t b = w->bytes;
+        delete w;
+        return set_error(GBGPU_E_NOMEM, "wBFS workspace of %zu bytes: %s", b, hipGetErrorString(e));
+    }
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char* p = (char*)w->block;
+    w->key = (unsigned long long*)p; p += al((size_t)g->n * 8);
+    w->Qs = (uint32_t*)p; p += al((size_t)NB * C * 4);
+    w->Ps = (uint32_t*)p; p += al((size_t)NB * C * 4);
+    w->sc = (unsigned long long*)p; p += al((size_t)NB * 8 * kSpreadStride);
+    w->ctl = (uint32_t*)p; p += al(64);
+    w->log = (uint32_t*)p;
+    if (hipHostMalloc((void**)&w->host_ctl, 64, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess) {
+        free_wbfs_ws(w);
+        return set_error(GBGPU_E_HIP, "wBFS workspace: pinned buffer or event creation failed");
+    }
+    g->wbfs = w;
+    return GBGPU_OK;
+}
+
+struct WbfsArgs {
+    const int64_t* off;
+    const int32_t* nbr;
+    const int32_t* wt;
+    const uint32_t* deg;
+    unsigned long long* key;
+    uint32_t* Qs;
+    uint32_t* Ps;
+    unsigned long long* sc;
+    uint32_t* ctl;
+    uint32_t* log;
+    int64_t n;
+    uint32_t NB;
+    uint32_t C;
+    uint32_t chunk_cap;
+};
+
+__global__ __launch_bounds__(kBlock) void wbfs_init_kernel(WbfsArgs a, uint32_t src) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = tid; v < a.n; v += stride) a.key[v] = v == src ? (unsigned long long)src : ~0ull;
+    for (int64_t i = tid; i < a.NB; i += stride)
+        a.sc[i * kSpreadStride] = i == 0 ? ((1ull << 32) | a.deg[src]) : 0ull;
+    if (tid == 0) {
+        a.Qs[0] = src;
+        a.Ps[0] = 0;
+        a.ctl[0] = 0;
+        a.ctl[1] = kStart;
+        a.ctl[2] = 0;
+        a.ctl[3] = 0;
+    }
+    for (int64_t i = tid; i < kWLogCap; i += stride) a.log[4 * i + 1] = 0;
+}
+
+// Workgroup staging of moved vertices: (vertex, new distance).  At the end of
+// the launch they are grouped by target bucket with a counting sort in LDS,
+// each non-empty target gets ONE packed reservation per workgroup, and a
+// workgroup scan produces the degree prefix sums within each target.
+constexpr int kMaxLdsNB = 256;
+constexpr int kWgCapW = 4096;  // LDS entries per workgroup (two workgroups per CU)
+
+struct WgBuckets {
+    uint32_t v[kWgCapW];
+    uint32_t d[kWgCapW];
+    uint32_t sv[kWgCapW];
+    uint32_t sdeg[kWgCapW];
+    uint32_t hcnt[kMaxLdsNB];
+    uint32_t hdeg[kMaxLdsNB];
+    uint32_t hoff[kMaxLdsNB + 1];
+    uint32_t hcur[kMaxLdsNB];
+    unsigned long long hbase[kMaxLdsNB];
+    uint32_t cnt;
+    uint32_t wsum[kRWaves];
+};
+
+__device__ __forceinline__ unsigned long long* slot_counter(const WbfsArgs& a, uint32_t t) {
+    return a.sc + (size_t)t * kSpreadStride;
+}
+
+// Wave-level fallback: lanes with the same target share one reservation.
+__device__ __forceinline__ void wave_bucket_emit(bool take, uint32_t v, uint32_t nd,
+                                                 const WbfsArgs& a) {
+    const int l = lane_id();
+    const uint32_t dv = take ? a.deg[v] : 0u;
+    const uint32_t t = nd & (a.NB - 1);
+    uint64_t pend = ballot(take);
+    while (pend) {
+        const int ld = first_lane(pend);
+        const uint32_t tt = __shfl(t, ld, 64);
+        const bool mine = take && t == tt;
+        const uint64_t mk = ballot(mine);
+        const uint32_t x = mine ? dv : 0u;
+        const uint32_t inc = wave_incl_sum(x);
+        const uint32_t tot = __shfl(inc, 63, 64);
+        unsigned long long packed = 0;
+        if (l == ld)
+            packed = atomicAdd(slot_counter(a, tt), ((unsigned long long)__popcll(mk) << 32) | tot);
+        packed = shfl64(packed, ld);
+        if (mine) {
+            const uint32_t pos = (uint32_t)(packed >> 32) + mbcnt(mk);
+            if (pos < a.C) {
+                a.Qs[(size_t)tt * a.C + pos] = v;
+                a.Ps[(size_t)tt * a.C + pos] = (uint32_t)packed + inc - x;
+            } else {
+                a.ctl[3] = 1u;
+            }
+        }
+        pend &= ~mk;
+    }
+}
+
+__device__ __forceinline__ void wgb_push(WgBuckets& q, bool take, uint32_t v, uint32_t nd,
+                                         const WbfsArgs& a) {
+    const uint64_t m = ballot(take);
+    if (!m) return;
+    const int l = lane_id();
+    const uint32_t k = (uint32_t)__popcll(m);
+    const int ld = first_lane(m);
+    uint32_t pos0 = kNone;
+    if (l == ld && a.NB <= (uint32_t)kMaxLdsNB) {
+        uint32_t old = *(volatile uint32_t*)&q.cnt;
+        for (;;) {
+            if (old + k > (uint32_t)kWgCapW) break;
+            uint32_t prev = atomicCAS(&q.cnt, old, old + k);
+            if (prev == old) {
+                pos0 = old;
+                break;
+            }
+            old = prev;
+        }
+    }
+    pos0 = __shfl(pos0, ld, 64);
+    if (pos0 != kNone) {
+        if (take) {
+            const uint32_t i = pos0 + mbcnt(m);
+            q.v[i] = v;
+            q.d[i] = nd;
+        }
+    } else {
+        wave_bucket_emit(take, v, nd, a);
+    }
+}
+
+// Workgroup-uniform: moves the buffered entries to their buckets and empties
+// the buffer.
+__device__ __forceinline__ void wgb_flush(WgBuckets& q, const WbfsArgs& a) {
+    __syncthreads();
+    const uint32_t n = q.cnt;
+    __syncthreads();  // every thread has read n before anyone can append again
+    if (n == 0) return;  // workgroup-uniform
+    const int t = threadIdx.x;
+    const int nt = blockDim.x;
+    const uint32_t NB = a.NB;
+    const uint32_t mask = NB - 1;
+    for (int i = t; i < (int)NB; i += nt) {
+        q.hcnt[i] = 0;
+        q.hdeg[i] = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < n; i += nt) {
+        const uint32_t tt = q.d[i] & mask;
+        atomicAdd(&q.hcnt[tt], 1u);
+        atomicAdd(&q.hdeg[tt], a.deg[q.v[i]]);
+    }
+    __syncthreads();
+    if (t < kWave) {
+        // exclusive scan of the per-target counts (NB <= 256)
+        uint32_t carry = 0;
+        for (uint32_t b0 = 0; b0 < NB; b0 += 64) {
+            const uint32_t i = b0 + (uint32_t)t;
+            const uint32_t x = i < NB ? q.hcnt[i] : 0u;
+            const uint32_t inc = wave_incl_sum(x);
+            if (i < NB) {
+                q.hoff[i] = carry + inc - x;
+                q.hcur[i] = carry + inc - x;
+            }
+            carry += __shfl(inc, 63, 64);
+        }
+        if (t == 0) q.hoff[NB] = carry;
+    }
+    for (int i = t; i < (int)NB; i += nt) {
+        const uint32_t c = q.hcnt[i];
+        unsigned long long packed = 0;
+        if (c) packed = atomicAdd(slot_counter(a, (uint32_t)i), ((unsigned long long)c << 32) | q.hdeg[i]);
+        q.hbase[i] = packed;
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < n; i += nt) {
+        const uint32_t tt = q.d[i] & mask;
+        const uint32_t pos = atomicAdd(&q.hcur[tt], 1u);
+        const uint32_t v = q.v[i];
+        q.sv[pos] = v;
+        q.sdeg[pos] = a.deg[v];
+    }
+    __syncthreads();
+    // workgroup exclusive scan over sdeg[0..n); result into q.v (free now)
+    constexpr int PER = kWgCapW / kRBlock;
+    const int l = lane_id();
+    const int wv = t / kWave;
+    uint32_t loc[PER];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t idx = (uint32_t)(PER * t + i);
+        const uint32_t x = idx < n ? q.sdeg[idx] : 0u;
+        loc[i] = s;
+        s += x;
+    }
+    const uint32_t inc = wave_incl_sum(s);
+    if (l == 63) q.wsum[wv] = inc;
+    __syncthreads();
+    if (t < kWave) {
+        const uint32_t x = t < kRWaves ? q.wsum[t] : 0u;
+        const uint32_t c = wave_incl_sum(x);
+        if (t < kRWaves) q.wsum[t] = c - x;
+    }
+    __syncthreads();
+    const uint32_t off = q.wsum[wv] + inc - s;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t idx = (uint32_t)(PER * t + i);
+        if (idx < n) q.v[idx] = off + loc[i];
+    }
+    __syncthreads();
+    // find the target of this thread's first position, then walk forward
+    const uint32_t p0 = (uint32_t)(PER * t);
+    if (p0 < n) {
+        uint32_t lo = 0, hi = NB;  // largest tt with hoff[tt] <= p0
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (q.hoff[mid] <= p0) lo = mid; else hi = mid;
+        }
+        uint32_t tt = lo;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t idx = p0 + (uint32_t)i;
+            if (idx >= n) break;
+            while (q.hoff[tt + 1] <= idx) ++tt;
+            const uint32_t seg = q.hoff[tt];
+            const unsigned long long hb = q.hbase[tt];
+            const uint32_t pos = (uint32_t)(hb >> 32) + (idx - seg);
+            if (pos < a.C) {
+                a.Qs[(size_t)tt * a.C + pos] = q.sv[idx];
+                a.Ps[(size_t)tt * a.C + pos] = (uint32_t)hb + q.v[idx] - q.v[seg];
+            } else {
+                a.ctl[3] = 1u;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) q.cnt = 0;
+    __syncthreads();
+}
+
+// Workgroup-uniform: flush when fewer than `room` free entries remain.
+__device__ __forceinline__ void wgb_maybe_flush(WgBuckets& q, const WbfsArgs& a, uint32_t room) {
+    __syncthreads();
+    const uint32_t n = q.cnt;
+    __syncthreads();
+    if (n + room > (uint32_t)kWgCapW) wgb_flush(q, a);
+}
+
+struct RelaxPolicy {
+    const WbfsArgs* a;
+    WgBuckets* q;
+    uint32_t b;
+    static constexpr bool kSkipDead = true;
+
+    // entry u of bucket b is live iff its current distance is still b
+    __device__ __forceinline__ uint32_t aux(uint32_t u) const {
+        return (uint32_t)(a->key[u] >> 32) == b ? 1u : 0u;
+    }
+
+    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t live, int64_t e) {
+        bool moved = false;
+        uint32_t v = 0, nd = 0;
+        if (act && live) {
+            v = (uint32_t)a->nbr[e];
+            nd = b + (uint32_t)a->wt[e];
+            const unsigned long long nk = ((unsigned long long)nd << 32) | u;
+            if (nk < a->key[v]) {
+                const unsigned long long old = atomicMin(&a->key[v], nk);
+                moved = nd < (uint32_t)(old >> 32);
+            }
+        }
+        wgb_push(*q, moved, v, nd, *a);
+    }
+
+    __device__ __forceinline__ void window_done() {}
+};
+
+__global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint32_t j) {
+    __shared__ WgBuckets q;
+    __shared__ uint32_t s_b;
+    const int l = lane_id();
+    const uint32_t bprev = a.ctl[(j + 1) & 1u];
+    if (threadIdx.x < 64) {
+        // nextBucket: smallest non-empty slot after the previous bucket
+        uint32_t b = kDone;
+        if (bprev != kDone) {
+            for (uint32_t k0 = 1; k0 < a.NB; k0 += 64) {
+                const uint32_t k = k0 + (uint32_t)l;
+                const bool ne =
+                    k < a.NB && (*slot_counter(a, (bprev + k) & (a.NB - 1)) >> 32) != 0;
+                const uint64_t mk = ballot(ne);
+                if (mk) {
+                    b = bprev + k0 + (uint32_t)first_lane(mk);
+                    break;
+                }
+            }
+        }
+        if (l == 0) {
+            s_b = b;
+            q.cnt = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t b = s_b;
+    const uint32_t slot = b & (a.NB - 1);
+    const unsigned long long packed = b == kDone ? 0ull : *slot_counter(a, slot);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctl[j & 1u] = b;
+        if (b == kDone) a.ctl[2] = 1u;
+        if (bprev != kStart && bprev != kDone) *slot_counter(a, bprev & (a.NB - 1)) = 0ull;
+        if (j < (uint32_t)kWLogCap) {
+            a.log[4 * j + 0] = b;
+            a.log[4 * j + 1] = b == kDone ? 0u : (uint32_t)(packed >> 32);
+            a.log[4 * j + 2] = (uint32_t)packed;
+            a.log[4 * j + 3] = 0u;
+        }
+    }
+    if (b == kDone) return;
+    const uint32_t cnt = (uint32_t)(packed >> 32);
+    const uint32_t E = (uint32_t)packed;
+    if (cnt > a.C) {
+        if (threadIdx.x == 0) a.ctl[3] = 1u;
+        return;
+    }
+    const uint32_t* Q = a.Qs + (size_t)slot * a.C;
+    const uint32_t* P = a.Ps + (size_t)slot * a.C;
+    const int wib = threadIdx.x / kWave;
+    const uint32_t nwaves = gridDim.x * kRWaves;
+    RelaxPolicy pol{&a, &q, b};
+    const uint32_t cap = min(a.chunk_cap, (uint32_t)(kWgCapW / (2 * kRWaves)));
+    const uint32_t wc = wave_chunk(E, nwaves, cap);
+    const uint32_t nchunks = (E + wc - 1) / wc;
+    const uint32_t ntiles = (nchunks + kRWaves - 1) / kRWaves;
+    // workgroup-uniform tiles of 16 chunks, so the LDS buffer can be flushed
+    // between tiles
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t c = tile * kRWaves + wib;
+        if (c < nchunks) {
+            const uint32_t eb = c * wc;
+            expand_range(Q, P, cnt, E, a.off, eb, min(E, eb + wc), pol);
+        }
+        wgb_maybe_flush(q, a, kRWaves * wc);
+    }
+    wgb_flush(q, a);
+}
+
+__global__ __launch_bounds__(kBlock) void wbfs_finalize_kernel(const unsigned long long* key,
+                                                               int64_t n, uint32_t* dist,
+                                                               int32_t* parent) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = tid; v < n; v += stride) {
+        const unsigned long long k = key[v];
+        dist[v] = (uint32_t)(k >> 32);
+        parent[v] = (int32_t)(uint32_t)k;
+    }
+}
+
+int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts& o,
+             gbgpu_stats* st, hipStream_t stream) {
+    const double t0 = now_ms();
+    const uint32_t NB = window_for(g->maxw, o.bucket_window);
+    uint32_t C = o.bucket_capacity > 0
+                     ? (uint32_t)std::min<int64_t>(o.bucket_capacity, g->n)
+                     : (uint32_t)std::min<int64_t>(g->n, std::max<int64_t>(4096, g->n / 4));
+    if (g->wbfs && g->wbfs->NB == NB && g->wbfs->C >= C && o.bucket_capacity <= 0) C = g->wbfs->C;
+    int retries = 0;
+    int launches = 0;
+    double kms = 0.0;
+    uint32_t j = 0;
+    for (;;) {
+        GB_TRY(ensure_wbfs_ws(g, NB, C));
+        WbfsWs* w = g->wbfs;
+        WbfsArgs a;
+        a.off = g->off;
+        a.nbr = g->nbr;
+        a.wt = g->w;
+        a.deg = g->deg;
+        a.key = w->key;
+        a.Qs = w->Qs;
+        a.Ps = w->Ps;
+        a.sc = w->sc;
+        a.ctl = w->ctl;
+        a.log = w->log;
+        a.n = g->n;
+        a.NB = NB;
+        a.C = C;
+        a.chunk_cap = (uint32_t)o.wave_chunk;
+        int igrid = (int)std::min<int64_t>(std::max<int64_t>((g->n + kBlock - 1) / kBlock, 64), 4096);
+        hipLaunchKernelGGL(wbfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, (uint32_t)src);
+        GB_HIP(hipGetLastError());
+        const int64_t work = std::max<int64_t>(1, g->m / 4096);
+        const int grid = (int)std::min<int64_t>(work, o.grid);
+        j = 0;
+        launches = 0;
+        kms = 0.0;
+        int K = std::max(16, o.rounds_per_sync);
+        bool overflow = false;
+        for (;;) {
+            if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
+            for (int i = 0; i < K; ++i)
+                hipLaunchKernelGGL(wbfs_step_kernel, dim3(grid), dim3(kRBlock), 0, stream, a, j + i);
+            GB_HIP(hipGetLastError());
+            if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
+            j += (uint32_t)K;
+            launches += K;
+            GB_HIP(hipMemcpyAsync(w->host_ctl, w->ctl, 16, hipMemcpyDeviceToHost, stream));
+            GB_HIP(hipStreamSynchronize(stream));
+            if (o.profile) {
+                float ms = 0.f;
+                GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+                kms += ms;
+            }
+            if (w->host_ctl[3]) { overflow = true; break; }
+            if (w->host_ctl[2]) break;
+            K = std::min(K * 2, 1024);
+        }
+        if (!overflow) {
+            hipLaunchKernelGGL(wbfs_finalize_kernel, dim3(igrid), dim3(kBlock), 0, stream, w->key,
+                               g->n, dist, parent);
+            GB_HIP(hipGetLastError());
+            GB_HIP(hipStreamSynchronize(stream));
+            break;
+        }
+        if (C >= (uint32_t)g->n)
+            return set_error(GBGPU_E_HIP, "bucket overflow at full capacity (internal error)");
+        C = (uint32_t)std::min<int64_t>(g->n, (int64_t)C * 2);
+        ++retries;
+    }
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        WbfsWs* w = g->wbfs;
+        std::vector<uint32_t> lg((size_t)std::min<uint32_t>(j, (uint32_t)kWLogCap) * 4);
+        if (!lg.empty()) {
+            GB_HIP(hipMemcpyAsync(lg.data(), w->log, lg.size() * 4, hipMemcpyDeviceToHost, stream));
+            GB_HIP(hipStreamSynchronize(stream));
+        }
+        for (size_t i = 0; i < lg.size() / 4; ++i) {
+            if (lg[4 * i] == kDone) break;
+            st->rounds++;
+            st->push_rounds++;
+            st->edges_examined += lg[4 * i + 2];
+        }
+        st->launches = launches;
+        st->kernel_ms = kms;
+        st->retries = retries;
+        st->wall_ms = now_ms() - t0;
+    }
+    return GBGPU_OK;
+}
+
+int wbfs_step_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps) {
+    if (!g->wbfs) { *nsteps = 0; return GBGPU_OK; }
+    int32_t k = std::min<int32_t>(max_steps, kWLogCap);
+    std::vector<uint32_t> lg((size_t)k * 4);
+    GB_HIP(hipMemcpy(lg.data(), g->wbfs->log, lg.size() * 4, hipMemcpyDeviceToHost));
+    int32_t r = 0;
+    while (r < k && lg[4 * r] != kDone && lg[4 * r + 1] != 0) ++r;
+    memcpy(out, lg.data(), (size_t)r * 16);
+    *nsteps = r;
+    return GBGPU_OK;
+}
+
+}  // namespace gb

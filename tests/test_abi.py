@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every function include/gbgpu.h
+declares (CPU only: no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gbgpu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gbgpu_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    import paper_1805_05208_amd as gb
+    if not os.path.exists(gb.LIB_PATH):
+        from paper_1805_05208_amd import _build
+        _build.build()
+    return gb.LIB_PATH
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["gbgpu_load_csr", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_submit", "gbgpu_poll",
+                     "gbgpu_bfs_multi", "gbgpu_bfs_batch", "gbgpu_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    L = ctypes.CDLL(libpath)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_names_match_header(libpath):
+    import paper_1805_05208_amd as gb
+    assert sorted(gb.EXPORTED) == declared_functions()
+
+
+def test_version_and_error_string(libpath):
+    import paper_1805_05208_amd as gb
+    L = gb.lib()
+    assert L.gbgpu_version() >= 10000
+    # a NULL graph is rejected before any device work
+    st = L.gbgpu_graph_info(None, None, None, None)
+    assert st == gb.E_INVALID
+    assert b"NULL" in L.gbgpu_last_error()

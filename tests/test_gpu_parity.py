@@ -1,0 +1,208 @@
+"""GPU parity: libgbgpu BFS / weighted BFS against the oracle, element by
+element (integer outputs: bit-exact distances and min-ID parents)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_05208_amd as m
+    m.lib()
+    return m
+
+
+def run_bfs(gb, G, src, opts=None):
+    d, p = gb.bfs(G, src, opts=opts)
+    return d.cpu().numpy(), p.cpu().numpy()
+
+
+def run_wbfs(gb, G, src, opts=None):
+    d, p = gb.wbfs(G, src, opts=opts)
+    return gb.as_u32(d), p.cpu().numpy()
+
+
+def assert_bfs(gb, g, G, src, opts=None, tag=""):
+    d, p = run_bfs(gb, G, src, opts)
+    od, op = oracle.bfs(g, src)
+    bad = np.nonzero((d != od) | (p != op))[0]
+    assert bad.size == 0, (f"{tag} src={src}: {bad.size} mismatches, first v={bad[0]}: "
+                           f"gpu ({d[bad[0]]},{p[bad[0]]}) oracle ({od[bad[0]]},{op[bad[0]]})")
+
+
+def assert_wbfs(gb, g, G, src, opts=None, tag=""):
+    d, p = run_wbfs(gb, G, src, opts)
+    od, op = oracle.wbfs(g, src)
+    bad = np.nonzero((d != od) | (p != op))[0]
+    assert bad.size == 0, (f"{tag} src={src}: {bad.size} mismatches, first v={bad[0]}: "
+                           f"gpu ({d[bad[0]]},{p[bad[0]]}) oracle ({od[bad[0]]},{op[bad[0]]})")
+
+
+def small_graphs():
+    out = [gg.path(1), gg.path(2), gg.path(17), gg.cycle(10), gg.cycle(11), gg.star(70),
+           gg.complete(9), gg.grid2d(13, 7), gg.torus3d(3), gg.torus3d(6)]
+    rng = np.random.default_rng(5)
+    for _ in range(12):
+        n = int(rng.integers(2, 40))
+        A = np.triu(rng.random((n, n)) < rng.uniform(0.05, 0.5), 1)
+        u, v = np.nonzero(A)
+        out.append(gg.from_edges(n, list(zip(u, v))))
+    return out
+
+
+def test_small_graphs_all_sources(gb):
+    rng = np.random.default_rng(9)
+    for g in small_graphs():
+        g.weights = gg.weights(g, 6, seed=4) if g.m else np.zeros(0, np.int32)
+        G = gb.Graph.from_csr(g)
+        for s in range(g.n):
+            assert_bfs(gb, g, G, s, tag=g.name)
+            if g.m:
+                assert_wbfs(gb, g, G, s, tag=g.name)
+        G.free()
+
+
+def test_golden_fixtures(gb):
+    import os
+    from test_oracle import _parse_golden, _vals
+    for name in ("small_unweighted.txt", "small_weighted.txt"):
+        g, src, rows = _parse_golden(name)
+        G = gb.Graph.from_csr(g)
+        d, p = run_bfs(gb, G, src)
+        assert np.array_equal(d.astype(np.int64), _vals(rows["bfs_dist"], 2**31 - 1))
+        assert np.array_equal(p.astype(np.int64), _vals(rows["bfs_parent"], -1))
+        if "wbfs_dist" in rows:
+            d, p = run_wbfs(gb, G, src)
+            assert np.array_equal(d.astype(np.int64), _vals(rows["wbfs_dist"], 0xFFFFFFFF))
+            assert np.array_equal(p.astype(np.int64), _vals(rows["wbfs_parent"], -1))
+
+
+@pytest.fixture(scope="module")
+def rmat16(gb):
+    g = gg.rmat(16, seed=1).with_weights(24, seed=2)
+    return g, gb.Graph.from_csr(g)
+
+
+def test_rmat16_bfs_sources(gb, rmat16):
+    g, G = rmat16
+    for s in gg.sources(g, 16, seed=3):
+        assert_bfs(gb, g, G, int(s), tag="rmat16")
+
+
+def test_rmat16_wbfs_sources(gb, rmat16):
+    g, G = rmat16
+    for s in gg.sources(g, 8, seed=3):
+        assert_wbfs(gb, g, G, int(s), tag="rmat16")
+
+
+@pytest.mark.parametrize("force", [1, 2, 3])
+def test_forced_directions_identical(gb, rmat16, force):
+    g, G = rmat16
+    for s in gg.sources(g, 4, seed=3):
+        assert_bfs(gb, g, G, int(s), opts={"force_direction": force}, tag=f"force{force}")
+
+
+@pytest.mark.parametrize("opts", [
+    {"wave_chunk": 64}, {"wave_chunk": 256, "grid": 7}, {"grid": 1}, {"grid": 3, "pull_light": 1},
+    {"pull_light": 4, "tau": 2}, {"tau": 1000}, {"rounds_per_sync": 1},
+])
+def test_tuning_knobs_identical(gb, rmat16, opts):
+    g, G = rmat16
+    for s in gg.sources(g, 3, seed=3):
+        assert_bfs(gb, g, G, int(s), opts=opts, tag=str(opts))
+        assert_wbfs(gb, g, G, int(s), opts=opts, tag=str(opts))
+
+
+@pytest.mark.parametrize("opts", [{"bucket_capacity": 64}, {"bucket_window": 256},
+                                  {"bucket_capacity": 1000, "grid": 5}])
+def test_bucket_knobs_identical(gb, rmat16, opts):
+    g, G = rmat16
+    for s in gg.sources(g, 2, seed=3):
+        assert_wbfs(gb, g, G, int(s), opts=opts, tag=str(opts))
+
+
+def test_repeat_runs_identical(gb, rmat16):
+    g, G = rmat16
+    s = int(gg.sources(g, 1, seed=3)[0])
+    d0, p0 = run_bfs(gb, G, s)
+    w0, q0 = run_wbfs(gb, G, s)
+    for _ in range(5):
+        d, p = run_bfs(gb, G, s)
+        assert np.array_equal(d, d0) and np.array_equal(p, p0)
+        w, q = run_wbfs(gb, G, s)
+        assert np.array_equal(w, w0) and np.array_equal(q, q0)
+
+
+def test_unit_weights_equal_bfs(gb):
+    g = gg.rmat(13, seed=4)
+    g.weights = np.ones(g.m, dtype=np.int32)
+    G = gb.Graph.from_csr(g)
+    for s in gg.sources(g, 3, seed=3):
+        d, p = run_bfs(gb, G, int(s))
+        w, q = run_wbfs(gb, G, int(s))
+        reach = d != 2**31 - 1
+        assert np.array_equal(w[reach].astype(np.int64), d[reach])
+        assert np.all(w[~reach] == 0xFFFFFFFF)
+        assert np.array_equal(p, q)
+
+
+def test_large_weights_and_isolated_source(gb):
+    g = gg.rmat(12, seed=6)
+    g.weights = gg.weights(g, 1000, seed=7)
+    G = gb.Graph.from_csr(g)
+    for s in gg.sources(g, 2, seed=3):
+        assert_wbfs(gb, g, G, int(s), tag="w1000")
+    iso = int(np.nonzero(g.degrees() == 0)[0][0])
+    assert_bfs(gb, g, G, iso, tag="isolated")
+    assert_wbfs(gb, g, G, iso, tag="isolated")
+
+
+def test_erdos_renyi_and_torus(gb):
+    for g in (gg.erdos_renyi(1 << 14, 32, seed=8), gg.torus3d(24)):
+        g.weights = gg.weights(g, 24, seed=2)
+        G = gb.Graph.from_csr(g)
+        for s in gg.sources(g, 2, seed=3):
+            assert_bfs(gb, g, G, int(s), tag=g.name)
+            assert_wbfs(gb, g, G, int(s), tag=g.name)
+
+
+def test_argument_errors(gb):
+    g = gg.path(5)
+    G = gb.Graph.from_csr(g)
+    with pytest.raises(gb.GbgpuError) as e:
+        gb.bfs(G, 5)
+    assert e.value.status == gb.E_INVALID
+    with pytest.raises(gb.GbgpuError) as e:
+        gb.wbfs(G, 0)  # no weights
+    assert e.value.status == gb.E_INVALID
+
+
+def test_validation_rejects_malformed_graphs(gb):
+    # asymmetric
+    with pytest.raises(gb.GbgpuError):
+        gb.Graph(np.array([0, 1, 1]), np.array([1], dtype=np.int32))
+    # unsorted list
+    with pytest.raises(gb.GbgpuError):
+        gb.Graph(np.array([0, 2, 3, 4]), np.array([2, 1, 0, 0], dtype=np.int32))
+    # self loop
+    with pytest.raises(gb.GbgpuError):
+        gb.Graph(np.array([0, 1, 1]), np.array([0], dtype=np.int32))
+    # bad offsets
+    with pytest.raises(gb.GbgpuError):
+        gb.Graph(np.array([0, 2, 1]), np.array([1, 0], dtype=np.int32))
+    # asymmetric weights
+    with pytest.raises(gb.GbgpuError):
+        gb.Graph(np.array([0, 1, 2]), np.array([1, 0], dtype=np.int32),
+                 np.array([3, 4], dtype=np.int32))
+    # zero weight
+    with pytest.raises(gb.GbgpuError):
+        gb.Graph(np.array([0, 1, 2]), np.array([1, 0], dtype=np.int32),
+                 np.array([0, 0], dtype=np.int32))
