@@ -82,7 +82,8 @@ typedef struct {
                                 overflow)                                       */
     int32_t rounds_per_sync; /* launches issued between host completion checks */
     int32_t profile;         /* 1: time each traversal launch with HIP events   */
-    int32_t reserved[7];
+    int32_t max_pending;     /* server: pending-queue bound (default 65536)     */
+    int32_t reserved[6];
 } gbgpu_opts;
 
 /* Per-call statistics (optional out-parameter). */
@@ -243,6 +244,10 @@ int gbgpu_debug_bfs_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_
  * bucket (distance), entries extracted (live and stale), sum of their
  * degrees, 0.  out holds max_steps * 4 words (host). */
 int gbgpu_debug_wbfs_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps);
+
+/* Host-only randomized self-test of the server's first-fit arena allocator
+ * (no device work); GBGPU_OK when every allocation matched a reference. */
+int gbgpu_debug_arena_selftest(uint64_t seed, int32_t steps);
 
 #ifdef __cplusplus
 }

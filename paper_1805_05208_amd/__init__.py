@@ -29,7 +29,7 @@ EXPORTED = [
     "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bfs_multi", "gbgpu_bfs_batch",
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
-    "gbgpu_debug_bfs_log", "gbgpu_debug_wbfs_log",
+    "gbgpu_debug_bfs_log", "gbgpu_debug_wbfs_log", "gbgpu_debug_arena_selftest",
 ]
 
 
@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
         ("pull_light", ctypes.c_int32), ("wave_chunk", ctypes.c_int32),
         ("grid", ctypes.c_int32), ("bucket_window", ctypes.c_int32),
         ("bucket_capacity", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
-        ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("profile", ctypes.c_int32), ("max_pending", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -108,6 +109,7 @@ def lib() -> ctypes.CDLL:
             "gbgpu_query_footprint": ([P, I32, P], ctypes.c_int),
             "gbgpu_debug_bfs_log": ([P, P, I32, P], ctypes.c_int),
             "gbgpu_debug_wbfs_log": ([P, P, I32, P], ctypes.c_int),
+            "gbgpu_debug_arena_selftest": ([U64, I32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):

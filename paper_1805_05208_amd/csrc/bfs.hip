@@ -39,12 +39,44 @@ struct BfsWs {
     uint32_t* F[3] = {nullptr, nullptr, nullptr};
     uint32_t* Q[2] = {nullptr, nullptr};
     uint32_t* P[2] = {nullptr, nullptr};
-    unsigned long long* ctl = nullptr;  // cnt[4], qcnt[4], qover[4] (as u64)
+    unsigned long long* ctl = nullptr;  // qcnt[4], qover[4] at +4/+8, totals at +64
     uint32_t* log = nullptr;            // kLogCap * 4
     unsigned long long* host_ctl = nullptr;  // pinned readback
-    void* block = nullptr;              // single device allocation
+    void* block = nullptr;              // owned device block (NULL when borrowed)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t bfs_ws_bytes(int64_t n, int64_t nwords) {
+    return al256((size_t)nwords * 4) * 4 + al256((size_t)(n + 64) * 4) * 4 +
+           al256((64 + 4 * kSpread * kSpreadStride) * 8) + al256((size_t)kLogCap * 16);
+}
+
+// Points the workspace at `mem` (bfs_ws_bytes(n, nwords) bytes of device
+// memory).  The memory stays owned by the caller.
+void bfs_ws_attach(BfsWs* w, void* mem, int64_t n, int64_t nwords) {
+    w->n = n;
+    w->nwords = nwords;
+    char* p = (char*)mem;
+    w->V = (uint32_t*)p; p += al256((size_t)nwords * 4);
+    for (int i = 0; i < 3; ++i) { w->F[i] = (uint32_t*)p; p += al256((size_t)nwords * 4); }
+    for (int i = 0; i < 2; ++i) { w->Q[i] = (uint32_t*)p; p += al256((size_t)(n + 64) * 4); }
+    for (int i = 0; i < 2; ++i) { w->P[i] = (uint32_t*)p; p += al256((size_t)(n + 64) * 4); }
+    w->ctl = (unsigned long long*)p; p += al256((64 + 4 * kSpread * kSpreadStride) * 8);
+    w->log = (uint32_t*)p;
+}
+
+// Host-side parts: pinned readback buffer and timing events.
+int bfs_ws_host_init(BfsWs* w) {
+    if (hipHostMalloc((void**)&w->host_ctl, kSpread * kSpreadStride * 8, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess)
+        return set_error(GBGPU_E_HIP, "BFS workspace: pinned buffer or event creation failed");
+    return GBGPU_OK;
+}
+
+BfsWs* bfs_ws_new() { return new BfsWs(); }
 
 void free_bfs_ws(BfsWs* w) {
     if (!w) return;
@@ -58,31 +90,18 @@ void free_bfs_ws(BfsWs* w) {
 static int ensure_bfs_ws(gbgpu_graph g) {
     if (g->bfs) return GBGPU_OK;
     BfsWs* w = new BfsWs();
-    w->n = g->n;
-    w->nwords = g->nwords;
-    size_t bm = (size_t)g->nwords * 4;
-    size_t qv = (size_t)(g->n + 64) * 4;
-    size_t ctl = (64 + 4 * kSpread * kSpreadStride) * 8;
-    size_t lg = (size_t)kLogCap * 4 * 4;
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t total = al(bm) * 4 + al(qv) * 4 + al(ctl) + al(lg);
+    const size_t total = bfs_ws_bytes(g->n, g->nwords);
     hipError_t e = hipMalloc(&w->block, total);
     if (e != hipSuccess) {
         delete w;
         return set_error(GBGPU_E_NOMEM, "BFS workspace of %zu bytes: %s", total,
                          hipGetErrorString(e));
     }
-    char* p = (char*)w->block;
-    w->V = (uint32_t*)p; p += al(bm);
-    for (int i = 0; i < 3; ++i) { w->F[i] = (uint32_t*)p; p += al(bm); }
-    for (int i = 0; i < 2; ++i) { w->Q[i] = (uint32_t*)p; p += al(qv); }
-    for (int i = 0; i < 2; ++i) { w->P[i] = (uint32_t*)p; p += al(qv); }
-    w->ctl = (unsigned long long*)p; p += al(ctl);
-    w->log = (uint32_t*)p;
-    if (hipHostMalloc((void**)&w->host_ctl, kSpread * kSpreadStride * 8, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess) {
+    bfs_ws_attach(w, w->block, g->n, g->nwords);
+    int s = bfs_ws_host_init(w);
+    if (s != GBGPU_OK) {
         free_bfs_ws(w);
-        return set_error(GBGPU_E_HIP, "BFS workspace: pinned buffer or event creation failed");
+        return s;
     }
     g->bfs = w;
     return GBGPU_OK;
@@ -463,11 +482,9 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     }
 }
 
-int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
-            const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream) {
+int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* parent,
+               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream) {
     const double t0 = now_ms();
-    GB_TRY(ensure_bfs_ws(g));
-    BfsWs* w = g->bfs;
     BfsArgs a;
     a.off = g->off;
     a.nbr = g->nbr;
@@ -550,6 +567,12 @@ int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
         st->wall_ms = now_ms() - t0;
     }
     return GBGPU_OK;
+}
+
+int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
+            gbgpu_stats* st, hipStream_t stream) {
+    GB_TRY(ensure_bfs_ws(g));
+    return run_bfs_ws(g, g->bfs, src, dist, parent, o, st, stream);
 }
 
 // Round log of the last BFS on this graph: 4 words per round (direction 1 =

@@ -70,6 +70,14 @@ struct gbgpu_graph_s {
 };
 
 namespace gb {
+// One BFS query of a batch: graph, source, output rows.
+struct MsQuery {
+    gbgpu_graph g;
+    int32_t src;
+    int32_t* dist;
+    int32_t* parent;
+};
+
 void free_bfs_ws(BfsWs* w);
 void free_wbfs_ws(WbfsWs* w);
 void free_multi_ws(MultiWs* w);

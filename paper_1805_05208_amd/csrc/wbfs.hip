@@ -53,7 +53,7 @@ struct WbfsWs {
     uint32_t* ctl = nullptr;   // [0..1] bucket of step j (j & 1), [2] done, [3] overflow
     uint32_t* log = nullptr;   // kWLogCap * 4
     uint32_t* host_ctl = nullptr;
-    void* block = nullptr;
+    void* block = nullptr;     // owned device block (NULL when borrowed)
     size_t bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -67,7 +67,7 @@ void free_wbfs_ws(WbfsWs* w) {
     delete w;
 }
 
-static uint32_t window_for(int32_t maxw, int32_t req) {
+uint32_t wbfs_window(int32_t maxw, int32_t req) {
     uint32_t need = 2u * (uint32_t)std::max(maxw, 1) + 1u;
     uint32_t nb = 2;
     while (nb < need) nb <<= 1;
@@ -79,39 +79,57 @@ static uint32_t window_for(int32_t maxw, int32_t req) {
     return nb;
 }
 
-size_t wbfs_bytes(int64_t n, uint32_t NB, uint32_t C) {
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    return al((size_t)n * 8) + 2 * al((size_t)NB * C * 4) + al((size_t)NB * 8 * kSpreadStride) + al(64) +
-           al((size_t)kWLogCap * 16);
+uint32_t wbfs_default_capacity(int64_t n) {
+    return (uint32_t)std::min<int64_t>(n, std::max<int64_t>(4096, n / 4));
 }
+
+static size_t wal(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t wbfs_bytes(int64_t n, uint32_t NB, uint32_t C) {
+    return wal((size_t)n * 8) + 2 * wal((size_t)NB * C * 4) +
+           wal((size_t)NB * 8 * kSpreadStride) + wal(64) + wal((size_t)kWLogCap * 16);
+}
+
+void wbfs_ws_attach(WbfsWs* w, void* mem, int64_t n, uint32_t NB, uint32_t C) {
+    w->n = n;
+    w->NB = NB;
+    w->C = C;
+    w->bytes = wbfs_bytes(n, NB, C);
+    char* p = (char*)mem;
+    w->key = (unsigned long long*)p; p += wal((size_t)n * 8);
+    w->Qs = (uint32_t*)p; p += wal((size_t)NB * C * 4);
+    w->Ps = (uint32_t*)p; p += wal((size_t)NB * C * 4);
+    w->sc = (unsigned long long*)p; p += wal((size_t)NB * 8 * kSpreadStride);
+    w->ctl = (uint32_t*)p; p += wal(64);
+    w->log = (uint32_t*)p;
+}
+
+int wbfs_ws_host_init(WbfsWs* w) {
+    if (hipHostMalloc((void**)&w->host_ctl, 64, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess)
+        return set_error(GBGPU_E_HIP, "wBFS workspace: pinned buffer or event creation failed");
+    return GBGPU_OK;
+}
+
+WbfsWs* wbfs_ws_new() { return new WbfsWs(); }
 
 static int ensure_wbfs_ws(gbgpu_graph g, uint32_t NB, uint32_t C) {
     if (g->wbfs && g->wbfs->NB == NB && g->wbfs->C == C) return GBGPU_OK;
     free_wbfs_ws(g->wbfs);
     g->wbfs = nullptr;
     WbfsWs* w = new WbfsWs();
-    w->n = g->n;
-    w->NB = NB;
-    w->C = C;
-    w->bytes = wbfs_bytes(g->n, NB, C);
-    hipError_t e = hipMalloc(&w->block, w->bytes);
+    const size_t bytes = wbfs_bytes(g->n, NB, C);
+    hipError_t e = hipMalloc(&w->block, bytes);
     if (e != hipSuccess) {
-        size_t b = w->bytes;
         delete w;
-        return set_error(GBGPU_E_NOMEM, "wBFS workspace of %zu bytes: %s", b, hipGetErrorString(e));
+        return set_error(GBGPU_E_NOMEM, "wBFS workspace of %zu bytes: %s", bytes,
+                         hipGetErrorString(e));
     }
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    char* p = (char*)w->block;
-    w->key = (unsigned long long*)p; p += al((size_t)g->n * 8);
-    w->Qs = (uint32_t*)p; p += al((size_t)NB * C * 4);
-    w->Ps = (uint32_t*)p; p += al((size_t)NB * C * 4);
-    w->sc = (unsigned long long*)p; p += al((size_t)NB * 8 * kSpreadStride);
-    w->ctl = (uint32_t*)p; p += al(64);
-    w->log = (uint32_t*)p;
-    if (hipHostMalloc((void**)&w->host_ctl, 64, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess) {
+    wbfs_ws_attach(w, w->block, g->n, NB, C);
+    int s = wbfs_ws_host_init(w);
+    if (s != GBGPU_OK) {
         free_wbfs_ws(w);
-        return set_error(GBGPU_E_HIP, "wBFS workspace: pinned buffer or event creation failed");
+        return s;
     }
     g->wbfs = w;
     return GBGPU_OK;
@@ -469,80 +487,64 @@ __global__ __launch_bounds__(kBlock) void wbfs_finalize_kernel(const unsigned lo
     }
 }
 
-int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts& o,
-             gbgpu_stats* st, hipStream_t stream) {
+// One weighted BFS on workspace w.  Sets *overflow (and leaves the outputs
+// unspecified) when a bucket outgrew the workspace's capacity.
+int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* parent,
+                const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool* overflow) {
     const double t0 = now_ms();
-    const uint32_t NB = window_for(g->maxw, o.bucket_window);
-    uint32_t C = o.bucket_capacity > 0
-                     ? (uint32_t)std::min<int64_t>(o.bucket_capacity, g->n)
-                     : (uint32_t)std::min<int64_t>(g->n, std::max<int64_t>(4096, g->n / 4));
-    if (g->wbfs && g->wbfs->NB == NB && g->wbfs->C >= C && o.bucket_capacity <= 0) C = g->wbfs->C;
-    int retries = 0;
+    WbfsArgs a;
+    a.off = g->off;
+    a.nbr = g->nbr;
+    a.wt = g->w;
+    a.deg = g->deg;
+    a.key = w->key;
+    a.Qs = w->Qs;
+    a.Ps = w->Ps;
+    a.sc = w->sc;
+    a.ctl = w->ctl;
+    a.log = w->log;
+    a.n = g->n;
+    a.NB = w->NB;
+    a.C = w->C;
+    a.chunk_cap = (uint32_t)o.wave_chunk;
+    const int igrid = (int)std::min<int64_t>(std::max<int64_t>((g->n + kBlock - 1) / kBlock, 64), 4096);
+    hipLaunchKernelGGL(wbfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, (uint32_t)src);
+    GB_HIP(hipGetLastError());
+    const int64_t work = std::max<int64_t>(1, g->m / 4096);
+    const int grid = (int)std::min<int64_t>(work, o.grid);
+    uint32_t j = 0;
     int launches = 0;
     double kms = 0.0;
-    uint32_t j = 0;
+    int K = std::max(16, o.rounds_per_sync);
+    *overflow = false;
     for (;;) {
-        GB_TRY(ensure_wbfs_ws(g, NB, C));
-        WbfsWs* w = g->wbfs;
-        WbfsArgs a;
-        a.off = g->off;
-        a.nbr = g->nbr;
-        a.wt = g->w;
-        a.deg = g->deg;
-        a.key = w->key;
-        a.Qs = w->Qs;
-        a.Ps = w->Ps;
-        a.sc = w->sc;
-        a.ctl = w->ctl;
-        a.log = w->log;
-        a.n = g->n;
-        a.NB = NB;
-        a.C = C;
-        a.chunk_cap = (uint32_t)o.wave_chunk;
-        int igrid = (int)std::min<int64_t>(std::max<int64_t>((g->n + kBlock - 1) / kBlock, 64), 4096);
-        hipLaunchKernelGGL(wbfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, (uint32_t)src);
+        if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
+        for (int i = 0; i < K; ++i)
+            hipLaunchKernelGGL(wbfs_step_kernel, dim3(grid), dim3(kRBlock), 0, stream, a, j + i);
         GB_HIP(hipGetLastError());
-        const int64_t work = std::max<int64_t>(1, g->m / 4096);
-        const int grid = (int)std::min<int64_t>(work, o.grid);
-        j = 0;
-        launches = 0;
-        kms = 0.0;
-        int K = std::max(16, o.rounds_per_sync);
-        bool overflow = false;
-        for (;;) {
-            if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
-            for (int i = 0; i < K; ++i)
-                hipLaunchKernelGGL(wbfs_step_kernel, dim3(grid), dim3(kRBlock), 0, stream, a, j + i);
-            GB_HIP(hipGetLastError());
-            if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
-            j += (uint32_t)K;
-            launches += K;
-            GB_HIP(hipMemcpyAsync(w->host_ctl, w->ctl, 16, hipMemcpyDeviceToHost, stream));
-            GB_HIP(hipStreamSynchronize(stream));
-            if (o.profile) {
-                float ms = 0.f;
-                GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-                kms += ms;
-            }
-            if (w->host_ctl[3]) { overflow = true; break; }
-            if (w->host_ctl[2]) break;
-            K = std::min(K * 2, 1024);
+        if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
+        j += (uint32_t)K;
+        launches += K;
+        GB_HIP(hipMemcpyAsync(w->host_ctl, w->ctl, 16, hipMemcpyDeviceToHost, stream));
+        GB_HIP(hipStreamSynchronize(stream));
+        if (o.profile) {
+            float ms = 0.f;
+            GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+            kms += ms;
         }
-        if (!overflow) {
-            hipLaunchKernelGGL(wbfs_finalize_kernel, dim3(igrid), dim3(kBlock), 0, stream, w->key,
-                               g->n, dist, parent);
-            GB_HIP(hipGetLastError());
-            GB_HIP(hipStreamSynchronize(stream));
-            break;
+        if (w->host_ctl[3]) {
+            *overflow = true;
+            return GBGPU_OK;
         }
-        if (C >= (uint32_t)g->n)
-            return set_error(GBGPU_E_HIP, "bucket overflow at full capacity (internal error)");
-        C = (uint32_t)std::min<int64_t>(g->n, (int64_t)C * 2);
-        ++retries;
+        if (w->host_ctl[2]) break;
+        K = std::min(K * 2, 1024);
     }
+    hipLaunchKernelGGL(wbfs_finalize_kernel, dim3(igrid), dim3(kBlock), 0, stream, w->key, g->n,
+                       dist, parent);
+    GB_HIP(hipGetLastError());
+    GB_HIP(hipStreamSynchronize(stream));
     if (st) {
         memset(st, 0, sizeof(*st));
-        WbfsWs* w = g->wbfs;
         std::vector<uint32_t> lg((size_t)std::min<uint32_t>(j, (uint32_t)kWLogCap) * 4);
         if (!lg.empty()) {
             GB_HIP(hipMemcpyAsync(lg.data(), w->log, lg.size() * 4, hipMemcpyDeviceToHost, stream));
@@ -556,6 +558,30 @@ int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const 
         }
         st->launches = launches;
         st->kernel_ms = kms;
+        st->wall_ms = now_ms() - t0;
+    }
+    return GBGPU_OK;
+}
+
+int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts& o,
+             gbgpu_stats* st, hipStream_t stream) {
+    const double t0 = now_ms();
+    const uint32_t NB = wbfs_window(g->maxw, o.bucket_window);
+    uint32_t C = o.bucket_capacity > 0 ? (uint32_t)std::min<int64_t>(o.bucket_capacity, g->n)
+                                       : wbfs_default_capacity(g->n);
+    if (g->wbfs && g->wbfs->NB == NB && g->wbfs->C >= C && o.bucket_capacity <= 0) C = g->wbfs->C;
+    int retries = 0;
+    for (;;) {
+        GB_TRY(ensure_wbfs_ws(g, NB, C));
+        bool overflow = false;
+        GB_TRY(run_wbfs_ws(g, g->wbfs, src, dist, parent, o, st, stream, &overflow));
+        if (!overflow) break;
+        if (C >= (uint32_t)g->n)
+            return set_error(GBGPU_E_HIP, "bucket overflow at full capacity (internal error)");
+        C = (uint32_t)std::min<int64_t>(g->n, (int64_t)C * 2);
+        ++retries;
+    }
+    if (st) {
         st->retries = retries;
         st->wall_ms = now_ms() - t0;
     }

@@ -51,3 +51,11 @@ def test_version_and_error_string(libpath):
     st = L.gbgpu_graph_info(None, None, None, None)
     assert st == gb.E_INVALID
     assert b"NULL" in L.gbgpu_last_error()
+
+
+def test_server_arena_allocator_selftest(libpath):
+    """The server's first-fit arena (host logic) against a reference bitmap."""
+    import paper_1805_05208_amd as gb
+    L = gb.lib()
+    for seed in range(1, 6):
+        assert L.gbgpu_debug_arena_selftest(seed, 4000) == gb.OK, L.gbgpu_last_error()

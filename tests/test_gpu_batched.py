@@ -1,0 +1,108 @@
+"""GPU parity for batched traversal: multi-source BFS (bit-packed frontiers)
+and the uneven multi-graph batch must equal the oracle row by row, and the
+single-source GPU path."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_05208_amd as m
+    m.lib()
+    return m
+
+
+def check_rows(g, srcs, D, P, tag=""):
+    D = D.cpu().numpy()
+    P = P.cpu().numpy()
+    for i, s in enumerate(srcs):
+        od, op = oracle.bfs(g, int(s))
+        bad = np.nonzero((D[i] != od) | (P[i] != op))[0]
+        assert bad.size == 0, (f"{tag} row {i} src {s}: {bad.size} mismatches, v={bad[0]} "
+                               f"gpu ({D[i][bad[0]]},{P[i][bad[0]]}) oracle ({od[bad[0]]},{op[bad[0]]})")
+
+
+@pytest.fixture(scope="module")
+def rmat14(gb):
+    g = gg.rmat(14, seed=21)
+    return g, gb.Graph.from_csr(g)
+
+
+@pytest.mark.parametrize("k", [1, 7, 64, 65, 130])
+def test_multi_source_matches_oracle(gb, rmat14, k):
+    g, G = rmat14
+    srcs = gg.sources(g, k, seed=3)
+    D, P = gb.bfs_multi(G, srcs)
+    check_rows(g, srcs, D, P, tag=f"k={k}")
+
+
+def test_multi_source_repeats_and_isolated(gb, rmat14):
+    g, G = rmat14
+    s = gg.sources(g, 5, seed=4)
+    iso = int(np.nonzero(g.degrees() == 0)[0][0])
+    srcs = np.array([s[0], s[1], s[0], iso, s[2], s[2], s[3]], dtype=np.int32)
+    D, P = gb.bfs_multi(G, srcs)
+    check_rows(g, srcs, D, P, tag="repeats")
+
+
+@pytest.mark.parametrize("force", [1, 2])
+def test_multi_source_forced_directions(gb, rmat14, force):
+    g, G = rmat14
+    srcs = gg.sources(g, 40, seed=5)
+    D, P = gb.bfs_multi(G, srcs, opts={"force_direction": force})
+    check_rows(g, srcs, D, P, tag=f"force{force}")
+
+
+def test_multi_source_equals_single_source_path(gb):
+    g = gg.rmat(16, seed=1)
+    G = gb.Graph.from_csr(g)
+    srcs = gg.sources(g, 64, seed=3)
+    D, P = gb.bfs_multi(G, srcs)
+    for i in (0, 17, 63):
+        d, p = gb.bfs(G, int(srcs[i]))
+        assert torch.equal(d, D[i]) and torch.equal(p, P[i])
+    check_rows(g, srcs[:8], D[:8], P[:8], tag="rmat16")
+
+
+def test_multi_source_torus_and_small(gb):
+    for g in (gg.torus3d(10), gg.cycle(12), gg.path(3), gg.star(5)):
+        G = gb.Graph.from_csr(g)
+        srcs = np.arange(min(g.n, 70), dtype=np.int32) % g.n
+        D, P = gb.bfs_multi(G, srcs)
+        check_rows(g, srcs, D, P, tag=g.name)
+
+
+def test_uneven_multi_graph_batch(gb):
+    scales = [8, 9, 10, 11, 12, 13, 14, 10]
+    graphs = [gg.rmat(s, seed=30 + i) for i, s in enumerate(scales)]
+    Gs = [gb.Graph.from_csr(g) for g in graphs]
+    qg, qs = [], []
+    for i, g in enumerate(graphs):
+        for s in gg.sources(g, 32 if i != 3 else 70, seed=40 + i):
+            qg.append(i)
+            qs.append(int(s))
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(qg))
+    qg = [qg[i] for i in order]
+    qs = [qs[i] for i in order]
+    dists, parents = gb.bfs_batch([Gs[i] for i in qg], qs)
+    for q in range(len(qg)):
+        od, op = oracle.bfs(graphs[qg[q]], qs[q])
+        assert np.array_equal(dists[q].cpu().numpy(), od), q
+        assert np.array_equal(parents[q].cpu().numpy(), op), q
+
+
+def test_batch_argument_errors(gb, rmat14):
+    g, G = rmat14
+    with pytest.raises(gb.GbgpuError):
+        gb.bfs_multi(G, [g.n])
+    with pytest.raises(gb.GbgpuError):
+        gb.bfs_multi(G, [])
