@@ -1,0 +1,360 @@
+"""Benchmark: direction-optimizing BFS on RMAT scale 24 (16 seeded sources).
+
+One step = one BFS from each of the 16 sources through gbgpu_bfs (inputs and
+outputs resident in HBM).  The JSON line reports Graph500 GTEPS (half the
+degree sum of the reached vertices per second), the roofline of the round
+kernel (algorithmic bytes / its HIP-event time, against 8 TB/s HBM), and the
+oracle timed on the host as the CPU baseline.  Extra sections (weighted BFS,
+the 3-D torus, batched queries, serving latency) are reported under "extra".
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--scale 24]
+       [--no-extra] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1805_05208_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1805_05208_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic byte model of one BFS (compulsory traffic of the method as run;
+# random per-edge status probes are not counted)
+# ---------------------------------------------------------------------------
+def edge_keys(g):
+    """Sorted (vertex << 32 | neighbour) keys of every stored edge, on the GPU
+    (bookkeeping for the byte model only)."""
+    import torch
+    src = torch.repeat_interleave(torch.arange(g.n, device="cuda", dtype=torch.int64),
+                                  torch.from_numpy(g.degrees()).cuda())
+    return (src << 32) | torch.from_numpy(g.nbrs).cuda().to(torch.int64)
+
+
+def parent_positions(g, keys, v, parent):
+    import torch
+    q = (torch.from_numpy(v.astype(np.int64)).cuda() << 32) | torch.from_numpy(
+        parent[v].astype(np.int64)).cuda()
+    return torch.searchsorted(keys, q).cpu().numpy() - g.offsets[v]
+
+
+def bfs_bytes(g, keys, dist, parent, rlog):
+    """Bytes of every round from the round log (direction, |U_r|, sum deg)
+    and the outputs (which fix each dense scan's stopping point)."""
+    n = g.n
+    deg = g.degrees()
+    INF = 2**31 - 1
+    reach = dist != INF
+    d = np.where(reach, dist, np.iinfo(np.int64).max).astype(np.int64)
+    # position of the parent in v's ascending list (dense scans stop there)
+    v = np.nonzero(reach & (parent != np.arange(n)))[0]
+    pos = np.zeros(n, dtype=np.int64)
+    pos[v] = parent_positions(g, keys, v, parent)
+    nz = deg > 0
+    total = 0
+    per_round = []
+    for r, (direction, cnt, edges, _q) in enumerate(rlog):
+        cnt_next = rlog[r + 1][1] if r + 1 < len(rlog) else 0
+        if direction == 2:  # dense
+            R = nz & (d > r)
+            found = R & (d == r + 1)
+            scan = np.where(found, pos + 1, deg)[R].sum()
+            b = 3 * n // 8 + 16 * int(R.sum()) + 4 * int(scan) + 8 * int(cnt_next)
+        elif direction == 3:  # sparse from the bitmap
+            b = n // 8 + 12 * int(cnt) + 4 * int(edges) + 16 * int(cnt_next)
+        else:  # sparse from the queue
+            b = 16 * int(cnt) + 4 * int(edges) + 16 * int(cnt_next)
+        per_round.append(b)
+        total += b
+    return total, per_round
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--sources", type=int, default=16)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--opts", type=str, default="", help="JSON gbgpu_opts overrides")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen as gg
+    import paper_1805_05208_amd as gb
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    gb.lib()
+    user_opts = json.loads(args.opts) if args.opts else {}
+
+    t = time.time()
+    g = gg.rmat(args.scale, seed=1)
+    srcs = [int(s) for s in gg.sources(g, args.sources, seed=3)]
+    log(f"generated rmat{args.scale}: n={g.n} m={g.m} in {time.time() - t:.1f}s")
+    G = gb.Graph.from_csr(g, validate=False, with_weights=False)
+    deg = g.degrees()
+    stream = torch.cuda.current_stream()
+
+    # --- correctness spot check + per-source edge counts -------------------
+    half_edges = []
+    outs = []
+    for s in srcs:
+        d, p = gb.bfs(G, s)
+        dn = d.cpu().numpy()
+        half_edges.append(int(deg[dn != 2**31 - 1].sum()) // 2)
+        outs.append((dn, p.cpu().numpy(), G.bfs_log()))
+    step_edges = sum(half_edges)
+
+    # --- warmup + timed steps ------------------------------------------------
+    popts = dict(user_opts)
+    popts["profile"] = 1
+    for _ in range(args.warmup):
+        for s in srcs:
+            gb.bfs(G, s, opts=user_opts)
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    launches = 0
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        for s in srcs:
+            _, _, st = gb.bfs(G, s, opts=popts, stats=True)
+            kernel_ms += st["kernel_ms"]
+            launches += st["launches"]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = wall * 1e3 / args.steps
+    gteps = step_edges * args.steps / wall / 1e9
+    log(f"BFS: {ms_per_step:.3f} ms/step ({len(srcs)} sources), {gteps:.1f} GTEPS, "
+        f"event time {gpu_ms / args.steps:.3f} ms/step")
+
+    # --- roofline of the round kernel ---------------------------------------
+    keys = edge_keys(g)
+    bytes_per_bfs = []
+    for (dn, pn, rl) in outs:
+        b, _ = bfs_bytes(g, keys, dn, pn, rl)
+        bytes_per_bfs.append(b)
+    del keys
+    alg_bytes = sum(bytes_per_bfs) * args.steps
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
+    roof = {
+        "kernel": "gb::bfs_round_kernel",
+        "bound": "hbm",
+        "achieved": round(achieved, 1) if achieved else None,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": None,
+        "bytes_per_launch": alg_bytes / max(launches, 1),
+        "avg_launch_us": kernel_ms * 1e3 / max(launches, 1),
+        "launches": launches,
+    }
+    tfile = os.path.join(PROFILES, "bfs_round_kernel_rmat24_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == kernel_source_hash():
+            roof["traffic"] = tr.get("bytes_per_launch")
+
+    # --- CPU baseline: the oracle on a bounded sample ---------------------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nsamp = 2
+        t = time.perf_counter()
+        for i in range(nsamp):
+            od, op = oracle.bfs(g, srcs[i])
+            assert np.array_equal(od, outs[i][0]) and np.array_equal(op, outs[i][1]), \
+                "GPU BFS differs from the oracle"
+        ct = time.perf_counter() - t
+        cpu = {"value": round(sum(half_edges[:nsamp]) / ct / 1e9, 4), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle",
+               "sample": f"sequential BFS + min-ID parent pass from {nsamp} of the {len(srcs)} "
+                         f"sources on rmat{args.scale} ({ct:.1f} s)"}
+        log(f"oracle: {cpu['value']} GTEPS on one core; GPU results identical on the sample")
+
+    extra = {}
+    if not args.no_extra:
+        extra = run_extras(g, G, srcs, gg, gb, torch, user_opts)
+
+    line = {
+        "metric": "GTEPS (direction-optimizing BFS, 1 GPU)",
+        "value": round(gteps, 2),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"BFS rmat{args.scale} ef16 (0.57,0.19,0.19,0.05) symmetrized, "
+                               f"{len(srcs)} seeded sources per step",
+                   "n": g.n, "m_directed": g.m, "sources": len(srcs),
+                   "edges_per_step_graph500": step_edges, "parallelism": "1 GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def timed(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best
+
+
+def run_extras(g, G, srcs, gg, gb, torch, user_opts):
+    extra = {}
+    deg = g.degrees()
+    # weighted BFS on the same graph, w in [1, 24)
+    try:
+        w = gg.weights(g, 24, seed=2)
+        Gw = gb.Graph(G.offsets, G.nbrs, w, validate=False)
+        tot_e, tot_t = 0, 0.0
+        for s in srcs[:4]:
+            d, p = gb.wbfs(Gw, s)
+            e = int(deg[gb.as_u32(d) != 0xFFFFFFFF].sum()) // 2
+            t = timed(lambda: gb.wbfs(Gw, s, opts=user_opts), reps=2)
+            tot_e += e
+            tot_t += t
+        extra["wbfs_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
+        extra["wbfs_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
+        log(f"wBFS rmat: {extra['wbfs_rmat24_gteps']} GTEPS, {extra['wbfs_rmat24_ms']} ms/source")
+        # batched: 64 sources in one call vs one at a time
+        s64 = [int(x) for x in gg.sources(g, 64, seed=3)]
+        tb = timed(lambda: gb.bfs_multi(G, s64), reps=2)
+        t1 = timed(lambda: [gb.bfs(G, s) for s in s64[:16]], reps=1) * 4
+        extra["batched64_qps"] = round(64 / tb, 1)
+        extra["single_qps"] = round(64 / t1, 1)
+        log(f"batched 64: {extra['batched64_qps']} q/s vs one-at-a-time {extra['single_qps']} q/s")
+        del Gw
+    except Exception as ex:  # noqa: BLE001 - extras must not hide the headline
+        extra["error_rmat"] = repr(ex)[:300]
+    try:
+        tg = gg.torus3d(256).with_weights(24, seed=2)
+        T = gb.Graph.from_csr(tg, validate=False)
+        ts = int(gg.sources(tg, 1, seed=3)[0])
+        tt = timed(lambda: gb.bfs(T, ts, opts=user_opts), reps=2)
+        tw = timed(lambda: gb.wbfs(T, ts, opts=user_opts), reps=1)
+        extra["torus256_bfs_ms"] = round(tt * 1e3, 3)
+        extra["torus256_bfs_gteps"] = round(tg.m / 2 / tt / 1e9, 3)
+        extra["torus256_wbfs_ms"] = round(tw * 1e3, 3)
+        log(f"torus: BFS {extra['torus256_bfs_ms']} ms, wBFS {extra['torus256_wbfs_ms']} ms")
+        del T
+    except Exception as ex:  # noqa: BLE001
+        extra["error_torus"] = repr(ex)[:300]
+    try:
+        extra.update(run_serving(g, G, gg, gb, torch))
+    except Exception as ex:  # noqa: BLE001
+        extra["error_serving"] = repr(ex)[:300]
+    return extra
+
+
+def run_serving(g, G, gg, gb, torch, nq=400):
+    """Poisson arrivals of mixed BFS/wBFS queries on resident graphs."""
+    graphs = [(g, G)]
+    g18 = gg.rmat(18, seed=1).with_weights(18, seed=2)
+    graphs.append((g18, gb.Graph.from_csr(g18, validate=False)))
+    tg = gg.torus3d(128).with_weights(21, seed=2)
+    graphs.append((tg, gb.Graph.from_csr(tg, validate=False)))
+    w24 = gg.weights(g, 24, seed=2)
+    Gw = gb.Graph(G.offsets, G.nbrs, w24, validate=False)
+    graphs[0] = (g, Gw)
+    sv = gb.Server(arena_bytes=24 << 30, max_inflight=8)
+    ids = [sv.add_graph(GG) for _, GG in graphs]
+    rng = np.random.default_rng(7)
+    srcsets = [gg.sources(h, 32, seed=3) for h, _ in graphs]
+    bufs = {}
+    for gi, (h, _) in enumerate(graphs):
+        bufs[gi] = [(torch.empty(h.n, dtype=torch.int32, device="cuda"),
+                     torch.empty(h.n, dtype=torch.int32, device="cuda")) for _ in range(16)]
+    # saturated throughput first: submit everything at once
+    def burst(count):
+        ts = []
+        t0 = time.perf_counter()
+        for i in range(count):
+            gi = int(rng.integers(0, len(graphs)))
+            kind = int(rng.integers(0, 2))
+            d, p = bufs[gi][i % 16]
+            ts.append(sv.submit(ids[gi], kind, int(srcsets[gi][i % 32]), d, p))
+        sv.drain()
+        for t in ts:
+            sv.poll(t)
+        return count / (time.perf_counter() - t0)
+    qps_sat = burst(nq // 2)
+    lam = 0.5 * qps_sat
+    lat = []
+    pend = []
+    t0 = time.perf_counter()
+    tnext = t0
+    for i in range(nq):
+        tnext += rng.exponential(1.0 / lam)
+        while time.perf_counter() < tnext:
+            pass
+        gi = int(rng.integers(0, len(graphs)))
+        kind = int(rng.integers(0, 2))
+        d, p = bufs[gi][i % 16]
+        pend.append(sv.submit(ids[gi], kind, int(srcsets[gi][i % 32]), d, p))
+    sv.drain()
+    el = time.perf_counter() - t0
+    for t in pend:
+        r = sv.poll(t)
+        lat.append((r["t_done_ns"] - r["t_arrive_ns"]) / 1e6)
+    sv.close()
+    lat = np.array(lat)
+    res = {"serving_saturated_qps": round(qps_sat, 1), "serving_lambda_qps": round(lam, 1),
+           "serving_qps": round(nq / el, 1), "serving_p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "serving_p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "serving_graphs": "rmat24 (w<24), rmat18 (w<18), torus128 (w<21); 50/50 BFS/wBFS"}
+    log(f"serving: {res}")
+    return res
+
+
+if __name__ == "__main__":
+    main()
