@@ -32,6 +32,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, only if the kernel sources have not changed since."""
+    import re
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if h and b and h.group(1) == kernel_source_hash():
+        return float(b.group(1))
+    return None
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_1805_05208_amd", "csrc"))):
@@ -101,6 +116,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--opts", type=str, default="", help="JSON gbgpu_opts overrides")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -116,6 +133,7 @@ def main():
     torch.cuda.set_device(0)
     gb.lib()
     user_opts = json.loads(args.opts) if args.opts else {}
+    tuned_path = os.path.join(ROOT, "paper_1805_05208_amd", "tuned.json")
 
     t = time.time()
     g = gg.rmat(args.scale, seed=1)
@@ -124,6 +142,14 @@ def main():
     G = gb.Graph.from_csr(g, validate=False, with_weights=False)
     deg = g.degrees()
     stream = torch.cuda.current_stream()
+    if not args.opts and not args.no_tuned:
+        from paper_1805_05208_amd import autotune
+        _, _, st0 = gb.bfs(G, srcs[0], stats=True)
+        sig = autotune.signature(g.n, g.m, int(deg.max()), st0["rounds"])
+        tuned = autotune.lookup(tuned_path, sig, "bfs")
+        if tuned:
+            user_opts = dict(tuned)
+            log(f"using autotuned options for {sig}: {tuned}")
 
     # --- correctness spot check + per-source edge counts -------------------
     half_edges = []
@@ -184,12 +210,7 @@ def main():
         "avg_launch_us": kernel_ms * 1e3 / max(launches, 1),
         "launches": launches,
     }
-    tfile = os.path.join(PROFILES, "bfs_round_kernel_rmat24_traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
-            tr = json.load(f)
-        if tr.get("source_hash") == kernel_source_hash():
-            roof["traffic"] = tr.get("bytes_per_launch")
+    roof["traffic"] = measured_traffic("bfs_round_kernel_rmat24_traffic.md")
 
     # --- CPU baseline: the oracle on a bounded sample ---------------------------
     cpu = None
@@ -231,6 +252,7 @@ def main():
                    "edges_per_step_graph500": step_edges, "parallelism": "1 GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "opts": user_opts,
         "extra": extra,
     }
     print(json.dumps(line), flush=True)

@@ -71,8 +71,10 @@ enum {
  * None of them changes results, only speed. */
 typedef struct {
     int32_t force_direction; /* 0 auto, 1 always push (sparse), 2 always pull
-                                (dense), 3 alternate push/pull by round       */
-    int32_t tau;             /* go dense when |U| + sum deg(U) > m / tau       */
+                                (dense), 3 alternate push/pull by round (wBFS:
+                                dense on odd buckets)                         */
+    int32_t tau;             /* go dense when |U| + sum deg(U) > m / tau (BFS
+                                frontier or wBFS bucket)                      */
     int32_t pull_light;      /* pull: neighbours one lane scans before the
                                 vertex is handed to a whole wavefront          */
     int32_t wave_chunk;      /* push: max edges per wavefront work item (>=64) */
@@ -240,9 +242,11 @@ int gbgpu_query_footprint(gbgpu_graph g, int32_t kind, size_t* bytes);
  * out holds max_rounds * 4 words (host). */
 int gbgpu_debug_bfs_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds);
 
-/* Per-bucket log of the last gbgpu_wbfs on g, 4 uint32 per bucket step:
- * bucket (distance), entries extracted (live and stale), sum of their
- * degrees, 0.  out holds max_steps * 4 words (host). */
+/* Per-launch log of the last gbgpu_wbfs on g, 4 uint32 per step launch:
+ * bucket (distance), entries in the bucket (live and stale), sum of their
+ * degrees, step kind (0 sparse push; a dense bucket takes two launches:
+ * 1 marks the bucket's vertices, 2 pulls).  out holds max_steps * 4 words
+ * (host). */
 int gbgpu_debug_wbfs_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps);
 
 /* Host-only randomized self-test of the server's first-fit arena allocator

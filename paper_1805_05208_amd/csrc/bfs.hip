@@ -123,6 +123,8 @@ struct BfsArgs {
     uint32_t* parent;
     unsigned long long* ctl;
     uint32_t* log;
+    const uint32_t* nz;     // vertices of nonzero degree
+    uint32_t nnz;
     int64_t n;
     int64_t nwords;
     uint64_t dense_thresh;  // go dense when |U| + sum deg(U) > dense_thresh
@@ -177,7 +179,7 @@ struct PushPolicy {
 
     __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
 
-    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e) {
+    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e, bool) {
         bool claim = false;
         uint32_t v = 0, dv = 0;
         if (act) {
@@ -210,54 +212,45 @@ __device__ __forceinline__ bool choose_push(const BfsArgs& a, uint32_t r, uint32
     return (uint64_t)count + edges <= a.dense_thresh;
 }
 
-// Dense (pull) processing of kPullG consecutive groups of 64 vertices by one
-// wavefront; lane l owns vertex 64*(g0+j)+l of each group j.  Each unvisited
-// vertex scans its list in ascending order and stops at the first member of
-// the frontier, which is its parent.  The groups are processed together so
-// that every lane keeps up to kPullG * 4 independent loads in flight.
+// Dense (pull) processing of kPullG x 64 entries of the list of vertices of
+// nonzero degree by one wavefront (lane l owns entries base + l + 64 j).
+// Each unvisited vertex scans its list in ascending order and stops at the
+// first member of the frontier, which is its parent.  The visited and
+// frontier words and the list bounds of all owned vertices are loaded in one
+// round trip, and the vertices are scanned together so that every lane keeps
+// several independent loads in flight.
 constexpr int kPullG = 2;
 
-__device__ __forceinline__ void pull_groups(const BfsArgs& a, uint32_t r, int64_t g0,
-                                            const uint32_t* __restrict__ Fc, uint32_t* Fn,
-                                            uint32_t* Fclr, uint32_t& found, uint32_t& dsum) {
+__device__ __forceinline__ void pull_entries(const BfsArgs& a, uint32_t r, uint32_t base,
+                                             const uint32_t* __restrict__ Fc, uint32_t* Fn,
+                                             uint32_t& found, uint32_t& dsum) {
     const int l = lane_id();
-    const int64_t ngroups = a.nwords / 2;
-    uint32_t vw[kPullG];
+    uint32_t v[kPullG];
+    bool in[kPullG];
+#pragma unroll
+    for (int j = 0; j < kPullG; ++j) {
+        const uint32_t i = base + (uint32_t)l + 64u * j;
+        in[j] = i < a.nnz;
+        v[j] = in[j] ? a.nz[i] : 0u;
+    }
     bool unvis[kPullG];
-    bool any = false;
-#pragma unroll
-    for (int j = 0; j < kPullG; ++j) {
-        const int64_t w = 2 * (g0 + j) + (l >> 5);
-        vw[j] = (g0 + j < ngroups) ? (a.V[w] | Fc[w]) : ~0u;
-    }
-#pragma unroll
-    for (int j = 0; j < kPullG; ++j) {
-        const int64_t w = 2 * (g0 + j) + (l >> 5);
-        const int64_t v = 64 * (g0 + j) + l;
-        if (g0 + j < ngroups && (l & 31) == 0) {
-            a.V[w] = vw[j];
-            Fclr[w] = 0u;
-        }
-        unvis[j] = v < a.n && !((vw[j] >> (l & 31)) & 1u);
-        any |= unvis[j];
-    }
-    if (ballot(any) == 0) {
-#pragma unroll
-        for (int j = 0; j < kPullG; ++j)
-            if (g0 + j < ngroups && (l & 31) == 0) Fn[2 * (g0 + j) + (l >> 5)] = 0u;
-        return;
-    }
     int64_t s[kPullG], e[kPullG], k[kPullG], lim[kPullG];
     uint32_t hit[kPullG];
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
-        const uint32_t v = (uint32_t)(64 * (g0 + j) + l);
-        s[j] = unvis[j] ? a.off[v] : 0;
-        e[j] = unvis[j] ? a.off[v + 1] : 0;
-        lim[j] = min(e[j], s[j] + (int64_t)a.light);
+        uint32_t vw = ~0u;
+        s[j] = e[j] = 0;
+        if (in[j]) {
+            vw = a.V[v[j] >> 5] | Fc[v[j] >> 5];
+            s[j] = a.off[v[j]];
+            e[j] = a.off[v[j] + 1];
+        }
+        unvis[j] = in[j] && !((vw >> (v[j] & 31)) & 1u);
+        lim[j] = unvis[j] ? min(e[j], s[j] + (int64_t)a.light) : s[j];
         k[j] = s[j];
         hit[j] = kNone;
     }
+    if (ballot(unvis[0] || unvis[kPullG - 1]) == 0) return;
     // light phase: lanes scan up to `light` neighbours of each of their
     // vertices, four at a time, in ascending order
     for (;;) {
@@ -322,19 +315,12 @@ __device__ __forceinline__ void pull_groups(const BfsArgs& a, uint32_t r, int64_
     }
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
-        const bool got = hit[j] != kNone;
-        if (got) {
-            const uint32_t v = (uint32_t)(64 * (g0 + j) + l);
-            a.dist[v] = (int32_t)(r + 1);
-            a.parent[v] = hit[j];
+        if (hit[j] != kNone) {
+            a.dist[v[j]] = (int32_t)(r + 1);
+            a.parent[v[j]] = hit[j];
+            atomicOr(&Fn[v[j] >> 5], 1u << (v[j] & 31));
             found += 1;
             dsum += (uint32_t)(e[j] - s[j]);
-        }
-        const uint64_t fm = ballot(got);
-        if (g0 + j < ngroups) {
-            const int64_t w = 2 * (g0 + j);
-            if (l == 0) Fn[w] = (uint32_t)fm;
-            if (l == 32) Fn[w + 1] = (uint32_t)(fm >> 32);
         }
     }
 }
@@ -461,14 +447,20 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
         }
         wgq_finish(q, out, true);
     } else {
-        // dense round: each wavefront owns groups of 64 consecutive vertices;
-        // the output is the bitmap only
+        // dense round over the list of vertices of nonzero degree; the
+        // output is the bitmap only.  First fold U_r into V (leaves V | F_r
+        // unchanged) and clear the bitmap that round r+1 writes.
         if (blockIdx.x == 0 && threadIdx.x == 0) *out.qover = 1ull;
+        for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwords;
+             w += (int64_t)gridDim.x * blockDim.x) {
+            const uint32_t fw = Fc[w];
+            if (fw) a.V[w] |= fw;
+            Fclr[w] = 0u;
+        }
         uint32_t found = 0, dsum = 0;
-        const int64_t ngroups = a.nwords / 2;
-        const int64_t nquads = (ngroups + kPullG - 1) / kPullG;
-        for (int64_t qi = gwave; qi < nquads; qi += nwaves)
-            pull_groups(a, r, qi * kPullG, Fc, Fn, Fclr, found, dsum);
+        const uint32_t per = 64u * kPullG;
+        for (uint32_t base = gwave * per; base < a.nnz; base += nwaves * per)
+            pull_entries(a, r, base, Fc, Fn, found, dsum);
         found = wave_sum(found);
         dsum = wave_sum(dsum);
         if (l == 0 && found) {
@@ -501,6 +493,8 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.parent = (uint32_t*)parent;
     a.ctl = w->ctl;
     a.log = w->log;
+    a.nz = g->nz;
+    a.nnz = g->nnz;
     a.n = g->n;
     a.nwords = g->nwords;
     a.dense_thresh = (uint64_t)g->m / (uint64_t)o.tau;

@@ -64,6 +64,11 @@ struct gbgpu_graph_s {
     int device = 0;
     int num_cus = 256;
     std::mutex mu;               // serialises calls sharing the workspaces
+    std::mutex plan_mu;          // guards the lazily built pull plan
+    uint4* plan = nullptr;       // owned: dense-scan work items (see ensure_pull_plan)
+    uint32_t nplan = 0;
+    uint32_t* nz = nullptr;      // owned: ids of the vertices of nonzero degree, ascending
+    uint32_t nnz = 0;
     gb::BfsWs* bfs = nullptr;
     gb::WbfsWs* wbfs = nullptr;
     gb::MultiWs* multi = nullptr;
@@ -84,6 +89,9 @@ void free_multi_ws(MultiWs* w);
 double now_ms();
 int64_t now_ns();
 gbgpu_opts resolve_opts(const gbgpu_opts* o);
+int ensure_pull_plan(gbgpu_graph g);
+constexpr uint32_t kPlanCap = 1024;   // max edges of one dense-scan work item
+constexpr uint32_t kPlanHub = 0xFFFFFFFFu;
 }  // namespace gb
 
 // ---------------------------------------------------------------------------
@@ -165,7 +173,9 @@ __device__ __forceinline__ uint32_t wave_search(const uint32_t* __restrict__ P, 
 // loading 64 frontier entries at once and finding each lane's entry with a
 // six-step shuffle search.  Policy provides:
 //   uint32_t aux(uint32_t u)             per-entry value (e.g. a stale flag)
-//   void edge(bool act, uint32_t u, uint32_t aux, int64_t e)
+//   void edge(bool act, uint32_t u, uint32_t aux, int64_t e, bool first)
+//                                        first: e is u's first edge (exactly
+//                                        one lane over the whole range sees it)
 //   void window_done()                   after each window of <= 64 edges
 //   static constexpr bool kSkipDead      skip edge ranges of entries whose
 //                                        aux() is 0 without visiting them
@@ -230,7 +240,7 @@ __device__ __forceinline__ void expand_range(const uint32_t* __restrict__ Q,
         const uint32_t a = __shfl(myA, o, 64);
         const int64_t s0 = (int64_t)shfl64((uint64_t)myS, o);
         const uint32_t p0 = __shfl(myP, o, 64);
-        pol.edge(act, u, a, s0 + (int64_t)(t - p0));
+        pol.edge(act, u, a, s0 + (int64_t)(t - p0), act && t == p0);
         pol.window_done();
         e = min(e + 64u, lim);
         if (e < e_end && e < endLoaded && (uint64_t)e + 63u >= endLoaded) {
@@ -247,7 +257,10 @@ __device__ __forceinline__ void expand_range(const uint32_t* __restrict__ Q,
 
 // Expansion of up to 64 frontier entries held in lanes (vertex u, list start,
 // degree): their edges are concatenated and walked 64 at a time with the same
-// shuffle search as expand_range.  Wave-uniform.
+// shuffle search as expand_range.  Lanes that are not valid, or have degree
+// 0, may sit anywhere: their prefix equals the next lane's, and the search
+// returns the largest lane whose prefix is <= the edge index, which always
+// owns edges.  Wave-uniform.
 template <typename Policy>
 __device__ __forceinline__ void expand_lanes(bool valid, uint32_t u, int64_t start, uint32_t deg,
                                              Policy& pol) {
@@ -255,7 +268,7 @@ __device__ __forceinline__ void expand_lanes(bool valid, uint32_t u, int64_t sta
     const uint32_t d = valid ? deg : 0u;
     const uint32_t inc = wave_incl_sum(d);
     const uint32_t T = __shfl(inc, 63, 64);
-    const uint32_t myP = valid ? inc - d : 0xFFFFFFFFu;
+    const uint32_t myP = inc - d;
     for (uint32_t e = 0; e < T; e += 64) {
         const uint32_t t = e + (uint32_t)l;
         const bool act = t < T;
@@ -268,7 +281,7 @@ __device__ __forceinline__ void expand_lanes(bool valid, uint32_t u, int64_t sta
         const uint32_t uo = __shfl(u, o, 64);
         const int64_t so = (int64_t)shfl64((uint64_t)start, o);
         const uint32_t po = __shfl(myP, o, 64);
-        pol.edge(act, uo, 1u, so + (int64_t)(t - po));
+        pol.edge(act, uo, 1u, so + (int64_t)(t - po), act && t == po);
         pol.window_done();
     }
 }

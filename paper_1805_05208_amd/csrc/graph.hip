@@ -146,6 +146,71 @@ __global__ void degree_kernel(const int64_t* off, int64_t n, int64_t nwords, uin
     }
 }
 
+// Dense-scan plan: work items that cover every non-isolated vertex once.
+// An item is either a run of at most 64 consecutive vertices with at most
+// kPlanCap edges in total ({first, end, kPlanHub, 0}), or a piece of at most
+// kPlanCap edges of one vertex whose list is longer ({v, v + 1, first_edge,
+// end_edge}).  Runs of isolated vertices are skipped.
+int ensure_pull_plan(gbgpu_graph g) {
+    std::lock_guard<std::mutex> lk(g->plan_mu);
+    if (g->plan) return GBGPU_OK;
+    std::vector<int64_t> off((size_t)g->n + 1);
+    GB_HIP(hipMemcpy(off.data(), g->off, off.size() * 8, hipMemcpyDeviceToHost));
+    std::vector<uint4> items;
+    items.reserve((size_t)(g->m / kPlanCap + g->n / 64 + 16));
+    int64_t i = 0;
+    const int64_t n = g->n;
+    while (i < n) {
+        const int64_t d = off[i + 1] - off[i];
+        if (d == 0) {
+            ++i;
+            continue;
+        }
+        if (d > (int64_t)kPlanCap) {
+            for (int64_t e = off[i]; e < off[i + 1]; e += kPlanCap)
+                items.push_back(make_uint4((uint32_t)i, (uint32_t)(i + 1), (uint32_t)e,
+                                           (uint32_t)std::min<int64_t>(e + kPlanCap, off[i + 1])));
+            ++i;
+            continue;
+        }
+        const int64_t vb = i;
+        int64_t edges = 0;
+        while (i < n && i - vb < 64) {
+            const int64_t di = off[i + 1] - off[i];
+            if (di > (int64_t)kPlanCap || edges + di > (int64_t)kPlanCap) break;
+            edges += di;
+            ++i;
+        }
+        items.push_back(make_uint4((uint32_t)vb, (uint32_t)i, kPlanHub, 0u));
+    }
+    std::vector<uint32_t> nzv;
+    nzv.reserve((size_t)n);
+    for (int64_t v = 0; v < n; ++v)
+        if (off[v + 1] > off[v]) nzv.push_back((uint32_t)v);
+    uint32_t* d_nz = nullptr;
+    if (hipMalloc(&d_nz, std::max<size_t>(nzv.size(), 1) * 4) != hipSuccess)
+        return set_error(GBGPU_E_NOMEM, "vertex list allocation failed");
+    if (!nzv.empty() && hipMemcpy(d_nz, nzv.data(), nzv.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d_nz);
+        return set_error(GBGPU_E_HIP, "vertex list upload failed");
+    }
+    uint4* d_items = nullptr;
+    if (hipMalloc(&d_items, std::max<size_t>(items.size(), 1) * sizeof(uint4)) != hipSuccess) {
+        (void)hipFree(d_nz);
+        return set_error(GBGPU_E_NOMEM, "dense-scan plan allocation failed");
+    }
+    if (!items.empty() &&
+        hipMemcpy(d_items, items.data(), items.size() * sizeof(uint4), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d_items);
+        return set_error(GBGPU_E_HIP, "dense-scan plan upload failed");
+    }
+    g->plan = d_items;
+    g->nplan = (uint32_t)items.size();
+    g->nz = d_nz;
+    g->nnz = (uint32_t)nzv.size();
+    return GBGPU_OK;
+}
+
 static int grid_for(int64_t items) {
     int64_t g = (items + kBlock - 1) / kBlock;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
@@ -243,6 +308,8 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
         return fail(set_error(GBGPU_E_HIP, "degree kernel failed"));
     (void)hipFree(scratch);
     scratch = nullptr;
+    int ps = ensure_pull_plan(g);
+    if (ps != GBGPU_OK) return fail(ps);
     *out = g;
     return GBGPU_OK;
 }
@@ -254,6 +321,8 @@ int gbgpu_graph_free(gbgpu_graph g) {
         free_bfs_ws(g->bfs);
         free_wbfs_ws(g->wbfs);
         free_multi_ws(g->multi);
+        if (g->plan) (void)hipFree(g->plan);
+        if (g->nz) (void)hipFree(g->nz);
         (void)hipFree(g->deg);
         (void)hipFree(g->zmask);
     }

@@ -40,6 +40,11 @@ struct MsGroupDev {
     unsigned long long* ctl;    // [0..3] qcnt, [4..7] qover, then 4 x kSpread x kSpreadStride totals
     int32_t* const* drow;       // 64 row pointers (dist), device array
     int32_t* const* prow;       // 64 row pointers (parent), device array
+    const uint4* plan;          // dense-scan work items of the graph
+    uint32_t nplan;
+    uint32_t k;                 // sources in the group
+    uint32_t* PS;               // vertex-major parents, PS[v * k + j]
+    uint32_t* DS;               // vertex-major distances, DS[v * k + j]
 };
 
 struct MsArgs {
@@ -92,18 +97,19 @@ __global__ __launch_bounds__(kBlock) void ms_init_kernel(MsGroupDev* groups, int
         G.F[1][v] = 0ull;
         G.F[2][v] = 0ull;
     }
-    for (int j = 0; j < k; ++j) {
-        int32_t* dr = G.drow[j];
-        int32_t* pr = G.prow[j];
-        for (int64_t v = tid; v < G.n; v += stride) {
-            dr[v] = INT32_MAX;
-            pr[v] = v == (int64_t)srcs[j] ? (int32_t)srcs[j] : -1;
-        }
-    }
+    // parents start at "none" so sparse rounds can take atomicMin; distances
+    // need no initialisation (written once per reached pair, and the final
+    // transpose reads them only for reached pairs)
+    const int64_t tot = G.n * (int64_t)G.k;
+    uint4* ps4 = (uint4*)G.PS;
+    for (int64_t i = tid; i < tot / 4; i += stride) ps4[i] = make_uint4(kNone, kNone, kNone, kNone);
+    for (int64_t i = (tot / 4) * 4 + tid; i < tot; i += stride) G.PS[i] = kNone;
     for (int64_t i = tid; i < 8 + 4 * kSpread * kSpreadStride; i += stride) G.ctl[i] = 0ull;
 }
 
-// After init: frontier F_0 = source bits, list Q_0 = distinct sources.
+// After init: frontier F_0 = source bits, list Q_0 = distinct sources; the
+// sources' own entries (distance 0, parent itself, visited) are set here so
+// that an isolated source needs no traversal work.
 __global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* srcs, int32_t k) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const MsGroupDev G = groups[gi];
@@ -117,9 +123,70 @@ __global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* s
             edges += G.deg[s];
         }
         G.F[0][s] |= 1ull << j;
+        G.VM[s] |= 1ull << j;
+        G.PS[(size_t)s * G.k + j] = s;
+        G.DS[(size_t)s * G.k + j] = 0;
     }
     G.ctl[0] = ((unsigned long long)cnt << 32) | edges;  // qcnt slot 0
     ms_tot(G, 0)[0] = ((unsigned long long)cnt << 32) | edges;
+}
+
+// Final layout: row j of the caller's output = source j.  Each workgroup
+// moves a tile of 64 vertices x k sources through LDS so both the
+// vertex-major reads and the row writes are coalesced; unreached pairs get
+// (INT32_MAX, -1).
+__global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups, int32_t gi) {
+    __shared__ uint32_t tp[64][65];
+    __shared__ uint32_t td[64][65];
+    __shared__ unsigned long long tv[64];
+    __shared__ int32_t* rd[64];
+    __shared__ int32_t* rp[64];
+    const MsGroupDev G = groups[gi];
+    const int k = (int)G.k;
+    const int t = threadIdx.x;
+    if (t < k) {
+        rd[t] = G.drow[t];
+        rp[t] = G.prow[t];
+    }
+    // thread t handles source column (t % 64) in the load phase and writes
+    // four consecutive vertices of row (t / 16 + 16 * pass) in the store phase
+    for (int64_t v0 = (int64_t)blockIdx.x * 64; v0 < G.n; v0 += (int64_t)gridDim.x * 64) {
+        const int nv = (int)min<int64_t>(64, G.n - v0);
+        __syncthreads();
+        if (t < nv) tv[t] = G.VM[v0 + t];
+        const int j = t & 63;
+        for (int vi = t >> 6; vi < nv; vi += kBlock / 64) {
+            if (j < k) {
+                tp[vi][j] = G.PS[(size_t)(v0 + vi) * k + j];
+                td[vi][j] = G.DS[(size_t)(v0 + vi) * k + j];
+            }
+        }
+        __syncthreads();
+        const int q = t & 15;  // four vertices 4q .. 4q+3
+        for (int row = t >> 4; row < k; row += kBlock / 16) {
+            const int vb = 4 * q;
+            if (vb >= nv) continue;
+            int32_t dv[4], pv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int vi = vb + i;
+                const bool reached = vi < nv && ((tv[vi < nv ? vi : 0] >> row) & 1ull);
+                dv[i] = reached ? (int32_t)td[vi][row] : INT32_MAX;
+                pv[i] = reached ? (int32_t)tp[vi][row] : -1;
+            }
+            int32_t* drow = rd[row] + v0 + vb;
+            int32_t* prow = rp[row] + v0 + vb;
+            if (vb + 4 <= nv && (((uintptr_t)drow | (uintptr_t)prow) & 15) == 0) {
+                *(int4*)drow = make_int4(dv[0], dv[1], dv[2], dv[3]);
+                *(int4*)prow = make_int4(pv[0], pv[1], pv[2], pv[3]);
+            } else {
+                for (int i = 0; i < 4 && vb + i < nv; ++i) {
+                    drow[i] = dv[i];
+                    prow[i] = pv[i];
+                }
+            }
+        }
+    }
 }
 
 struct MsPushPolicy {
@@ -133,7 +200,7 @@ struct MsPushPolicy {
 
     __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
 
-    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e) {
+    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e, bool) {
         bool claim = false;
         uint32_t v = 0, dv = 0;
         if (act) {
@@ -147,7 +214,7 @@ struct MsPushPolicy {
                 while (bits) {
                     const int j = __ffsll((long long)bits) - 1;
                     bits &= bits - 1;
-                    uint32_t* pp = (uint32_t*)G->prow[j] + v;
+                    uint32_t* pp = G->PS + (size_t)v * G->k + j;
                     if (u < *pp) atomicMin(pp, u);
                 }
                 if (claim) dv = G->deg[v];
@@ -165,104 +232,193 @@ struct MsPushPolicy {
     __device__ __forceinline__ void window_done() {}
 };
 
-// Dense processing of 64 consecutive vertices of one group by one wavefront.
-__device__ __forceinline__ void ms_pull_group(const MsGroupDev& G, uint32_t r, int64_t vg,
-                                              const unsigned long long* __restrict__ Fc,
-                                              unsigned long long* Fn, const QueueOut& out,
-                                              bool emit, int light, uint32_t& found,
-                                              uint32_t& dsum) {
+__device__ __forceinline__ unsigned long long shfl_up64(unsigned long long x, int d) {
+    const uint32_t lo = __shfl_up((uint32_t)x, d, 64);
+    const uint32_t hi = __shfl_up((uint32_t)(x >> 32), d, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, d, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), d, 64);
+        x |= ((unsigned long long)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Records the distance of the bits that entered the frontier (fold of F_r
+// into VM), one row per bit.
+__device__ __forceinline__ void ms_fold(const MsGroupDev& G, uint32_t r, uint32_t v,
+                                        unsigned long long vm, unsigned long long f) {
+    G.VM[v] = vm | f;
+    uint32_t* ds = G.DS + (size_t)v * G.k;
+    while (f) {
+        const int j = __ffsll((long long)f) - 1;
+        f &= f - 1;
+        ds[j] = r;
+    }
+}
+
+// Dense scan of one plan item that is a run of <= 64 vertices: the run's
+// edges are contiguous, so the wavefront walks them 64 at a time (coalesced
+// neighbour loads) and finds, for every vertex and every unseen bit, the
+// first neighbour in ascending order that carries the bit: a segmented
+// prefix-OR over the lanes of each vertex gives first contributors within a
+// window, and a per-vertex accumulator carries earlier windows.  A vertex
+// stops being scanned once all its unseen bits are found.
+__device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uint4 it,
+                                            const unsigned long long* __restrict__ Fc,
+                                            unsigned long long* Fn, const QueueOut& out,
+                                            bool emit, uint32_t& found, uint32_t& dsum) {
     const int l = lane_id();
-    const int64_t v64 = 64 * vg + l;
-    const bool inb = v64 < G.n;
-    const uint32_t v = (uint32_t)v64;
-    unsigned long long need = 0ull;
-    int64_t s = 0, e = 0;
-    if (inb) {
-        const unsigned long long f = Fc[v];
-        unsigned long long vm = G.VM[v];
-        if (f) {
-            // v's bits entered the frontier in round r: record the distance
-            vm |= f;
-            G.VM[v] = vm;
-            unsigned long long bits = f;
-            while (bits) {
-                const int j = __ffsll((long long)bits) - 1;
-                bits &= bits - 1;
-                G.drow[j][v] = (int32_t)r;
-            }
-        }
-        need = G.kmask & ~vm;
-        s = G.off[v];
-        e = G.off[v + 1];
-        if (s == e) need = 0ull;
+    const uint32_t vb = it.x, nv = it.y - it.x;
+    const bool in = (uint32_t)l < nv;
+    const uint32_t v = vb + (uint32_t)l;
+    const int64_t base = G.off[vb];
+    const uint32_t T = (uint32_t)(G.off[it.y] - base);
+    int64_t o0 = 0, o1 = 0;
+    unsigned long long f = 0, vm = 0;
+    if (in) {
+        o0 = G.off[v];
+        o1 = G.off[v + 1];
+        f = Fc[v];
+        vm = G.VM[v];
     }
+    const uint32_t s = in ? (uint32_t)(o0 - base) : 0xFFFFFFFFu;
+    const uint32_t d = (uint32_t)(o1 - o0);
+    if (in && f) ms_fold(G, r, v, vm, f);
+    const unsigned long long need = (in && d) ? (G.kmask & ~(vm | f)) : 0ull;
     unsigned long long acc = 0ull;
-    int64_t k = s;
-    const int64_t lim = min(e, s + (int64_t)light);
-    // light phase: one lane per vertex, ascending order, stop when all
-    // unseen bits are found
-    while (need && acc != need && k < lim) {
-        const uint32_t u = (uint32_t)G.nbr[k];
-        const unsigned long long add = Fc[u] & need & ~acc;
-        if (add) {
-            acc |= add;
-            unsigned long long bits = add;
-            while (bits) {
-                const int j = __ffsll((long long)bits) - 1;
-                bits &= bits - 1;
-                G.prow[j][v] = (int32_t)u;
-            }
+    uint64_t live = ballot(need != 0ull);
+    auto owner = [&](uint32_t x) {
+        int o = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1) {
+            const uint32_t pv = __shfl(s, o + st, 64);
+            if (pv <= x) o += st;
         }
-        ++k;
-    }
-    // heavy phase: the whole wavefront scans the rest of one list 64 at a
-    // time; a prefix OR over lanes gives each bit's first contributor
-    uint64_t hm = ballot(need && acc != need && k < e);
-    while (hm) {
-        const int h = first_lane(hm);
-        hm &= hm - 1;
-        const int64_t hs = (int64_t)shfl64((uint64_t)k, h);
-        const int64_t he = (int64_t)shfl64((uint64_t)e, h);
-        const unsigned long long hneed = shfl64(need, h);
-        unsigned long long hacc = shfl64(acc, h);
-        const uint32_t hv = __shfl(v, h, 64);
-        for (int64_t b = hs; b < he && hacc != hneed; b += 64) {
-            const int64_t i = b + l;
-            uint32_t u = 0;
-            unsigned long long add = 0ull;
-            if (i < he) {
-                u = (uint32_t)G.nbr[i];
-                add = Fc[u] & hneed & ~hacc;
+        return o;
+    };
+    uint32_t e = 0;
+    while (e < T && live) {
+        const int oe = owner(e);
+        if (!((live >> oe) & 1ull)) {
+            const uint64_t after = oe == 63 ? 0ull : (live & (~0ull << (oe + 1)));
+            if (!after) break;
+            e = max(e, __shfl(s, first_lane(after), 64));
+            continue;
+        }
+        // four windows: owners, then all loads, then the ordered updates
+        int ow[4];
+        uint32_t u[4];
+        unsigned long long fu[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t t = e + 64u * k + (uint32_t)l;
+            ow[k] = owner(t);
+            const bool act = t < T && ((live >> ow[k]) & 1ull);
+            u[k] = act ? (uint32_t)G.nbr[base + t] : kNone;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fu[k] = u[k] != kNone ? Fc[u[k]] : 0ull;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t eb = e + 64u * k;
+            if (eb >= T) break;
+            const int o = ow[k];
+            const unsigned long long acc_o = shfl64(acc, o);
+            const unsigned long long need_o = shfl64(need, o);
+            const unsigned long long add = fu[k] & need_o & ~acc_o;
+            const uint32_t so = __shfl(s, o, 64);
+            const int seg = so > eb ? (int)(so - eb) : 0;
+            unsigned long long incl = add;
+#pragma unroll
+            for (int st = 1; st < 64; st <<= 1) {
+                const unsigned long long y = shfl_up64(incl, st);
+                if (l - st >= seg) incl |= y;
             }
-            const unsigned long long before = wave_excl_or64(add);
-            unsigned long long first = add & ~before;
+            unsigned long long excl = shfl_up64(incl, 1);
+            if (l - 1 < seg) excl = 0ull;
+            unsigned long long first = add & ~excl;
+            uint32_t* ps = G.PS + (size_t)(vb + (uint32_t)o) * G.k;
             while (first) {
                 const int j = __ffsll((long long)first) - 1;
                 first &= first - 1;
-                G.prow[j][hv] = (int32_t)u;
+                ps[j] = u[k];
             }
-            unsigned long long all = add;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const uint32_t lo = __shfl_xor((uint32_t)all, d, 64);
-                const uint32_t hi = __shfl_xor((uint32_t)(all >> 32), d, 64);
-                all |= ((unsigned long long)hi << 32) | lo;
+            // each vertex takes the OR of its lanes in this window
+            uint32_t last = 0;
+            bool hasw = false;
+            if (in && d) {
+                const uint32_t a = s > eb ? s - eb : 0u;
+                const uint32_t endl = min(s + d, T);
+                if (s < eb + 64u && endl > eb) {
+                    last = min(endl - eb, 64u) - 1u;
+                    hasw = a <= last;
+                }
             }
-            hacc |= all;
+            const unsigned long long tot = shfl64(incl, (int)last);
+            if (hasw) acc |= tot;
         }
-        if (l == h) acc = hacc;
+        live = ballot(need != 0ull && acc != need);
+        e += 256u;
     }
-    if (inb) Fn[v] = acc;
     const bool got = acc != 0ull;
-    const uint32_t dv = got ? (uint32_t)(e - s) : 0u;
+    if (in && got) {
+        Fn[v] = acc;
+        found += 1;
+        dsum += d;
+    }
     const uint64_t m = ballot(got);
-    if (m) {
-        if (emit) wave_direct_emit(got, v, dv, m, out);
-        if (got) {
-            found += 1;
-            dsum += dv;
+    if (m && emit) wave_direct_emit(got, v, d, m, out);
+}
+
+// Dense scan of a piece of one long list: first contributors within the
+// piece, then atomicMin per bit across pieces (pieces of one list may run
+// concurrently); the next-frontier bits are OR-ed atomically and the piece
+// that sets the first bit counts the vertex.
+__device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, uint4 it,
+                                              const unsigned long long* __restrict__ Fc,
+                                              unsigned long long* Fn, const QueueOut& out,
+                                              bool emit, uint32_t& found, uint32_t& dsum) {
+    const int l = lane_id();
+    const uint32_t v = it.x;
+    const int64_t ob = G.off[v], oe = G.off[v + 1];
+    const unsigned long long f = Fc[v], vm = G.VM[v];
+    if ((int64_t)it.z == ob && f && l == 0) ms_fold(G, r, v, vm, f);
+    const unsigned long long need = G.kmask & ~(vm | f);
+    unsigned long long acc = 0ull;
+    for (uint32_t e = it.z; e < it.w && need && acc != need; e += 128u) {
+        const uint32_t t0 = e + (uint32_t)l, t1 = e + 64u + (uint32_t)l;
+        const uint32_t u0 = t0 < it.w ? (uint32_t)G.nbr[t0] : kNone;
+        const uint32_t u1 = t1 < it.w ? (uint32_t)G.nbr[t1] : kNone;
+        const unsigned long long f0 = u0 != kNone ? Fc[u0] : 0ull;
+        const unsigned long long f1 = u1 != kNone ? Fc[u1] : 0ull;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t u = k ? u1 : u0;
+            const unsigned long long add = (k ? f1 : f0) & need & ~acc;
+            unsigned long long first = add & ~wave_excl_or64(add);
+            while (first) {
+                const int j = __ffsll((long long)first) - 1;
+                first &= first - 1;
+                uint32_t* pp = G.PS + (size_t)v * G.k + j;
+                if (u < *pp) atomicMin(pp, u);
+            }
+            acc |= wave_or64(add);
         }
     }
+    bool claim = false;
+    if (l == 0 && acc) claim = atomicOr(&Fn[v], acc) == 0ull;
+    claim = __shfl((int)claim, 0, 64) != 0;
+    if (claim && l == 0) {
+        found += 1;
+        dsum += (uint32_t)(oe - ob);
+    }
+    const uint64_t m = ballot(claim && l == 0);
+    if (m && emit) wave_direct_emit(claim && l == 0, v, (uint32_t)(oe - ob), m, out);
 }
 
 __global__ __launch_bounds__(kRBlock, 8) void ms_round_kernel(MsArgs A, uint32_t r) {
@@ -316,7 +472,7 @@ __global__ __launch_bounds__(kRBlock, 8) void ms_round_kernel(MsArgs A, uint32_t
                     // the frontier itself must also be folded: one unit at least
                     units = max(1u, (edges + wc - 1) / wc);
                 } else {
-                    units = (uint32_t)((G.n + 63) / 64);
+                    units = G.nplan;
                 }
             }
             s_units[gi] = acc;
@@ -353,14 +509,7 @@ __global__ __launch_bounds__(kRBlock, 8) void ms_round_kernel(MsArgs A, uint32_t
             for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
                  i += gridDim.x * blockDim.x) {
                 const uint32_t u = Qc[i];
-                const unsigned long long f = Fc[u];
-                G.VM[u] |= f;
-                unsigned long long bits = f;
-                while (bits) {
-                    const int j = __ffsll((long long)bits) - 1;
-                    bits &= bits - 1;
-                    G.drow[j][u] = (int32_t)r;
-                }
+                ms_fold(G, r, u, G.VM[u], Fc[u]);
             }
         }
     }
@@ -394,7 +543,11 @@ __global__ __launch_bounds__(kRBlock, 8) void ms_round_kernel(MsArgs A, uint32_t
                 d0 = pol.dsum;
             }
         } else {
-            ms_pull_group(G, r, (int64_t)local, Fc, Fn, out, s_emit[gi] != 0, A.light, f0, d0);
+            const uint4 it = G.plan[local];
+            if (it.z == kPlanHub)
+                ms_pull_run(G, r, it, Fc, Fn, out, s_emit[gi] != 0, f0, d0);
+            else
+                ms_pull_piece(G, r, it, Fc, Fn, out, s_emit[gi] != 0, f0, d0);
         }
         f0 = wave_sum(f0);
         d0 = wave_sum(d0);
@@ -416,9 +569,10 @@ __global__ __launch_bounds__(kRBlock, 8) void ms_round_kernel(MsArgs A, uint32_t
 // ---------------------------------------------------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t ms_group_bytes(int64_t n) {
+size_t ms_group_bytes(int64_t n, int64_t k) {
     return 4 * al256((size_t)n * 8) + 4 * al256((size_t)(n + 64) * 4) +
-           al256((8 + 4 * kSpread * kSpreadStride) * 8) + 2 * al256(64 * 8) + al256(64 * 4);
+           al256((8 + 4 * kSpread * kSpreadStride) * 8) + 2 * al256(64 * 8) + al256(64 * 4) +
+           2 * al256((size_t)n * (size_t)k * 4);
 }
 
 // Packs queries on the same graph 64 to a group (in submission order).
@@ -452,11 +606,12 @@ static size_t ms_header_bytes(int NG) {
 static size_t ms_chunk_bytes(const std::vector<MsQuery>& qs,
                              const std::vector<std::vector<int>>& groups, size_t g0, int NG) {
     size_t bytes = ms_header_bytes(NG);
-    for (int i = 0; i < NG; ++i) bytes += ms_group_bytes(qs[groups[g0 + i][0]].g->n);
+    for (int i = 0; i < NG; ++i)
+        bytes += ms_group_bytes(qs[groups[g0 + i][0]].g->n, (int64_t)groups[g0 + i].size());
     return bytes;
 }
 
-size_t ms_query_bytes(int64_t n) { return ms_header_bytes(1) + ms_group_bytes(n); }
+size_t ms_query_bytes(int64_t n, int64_t k) { return ms_header_bytes(1) + ms_group_bytes(n, k); }
 
 size_t ms_pin_bytes() { return (size_t)kMaxGroups * kSpread * kSpreadStride * 8; }
 
@@ -486,6 +641,9 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         G.n = n;
         G.dense_thresh = (uint64_t)g->m / (uint64_t)o.tau;
         G.kmask = gq.size() == 64 ? ~0ull : ((1ull << gq.size()) - 1ull);
+        GB_TRY(ensure_pull_plan(g));
+        G.plan = g->plan;
+        G.nplan = g->nplan;
         G.VM = (unsigned long long*)p; p += al256((size_t)n * 8);
         for (int b = 0; b < 3; ++b) { G.F[b] = (unsigned long long*)p; p += al256((size_t)n * 8); }
         for (int b = 0; b < 2; ++b) { G.Q[b] = (uint32_t*)p; p += al256((size_t)(n + 64) * 4); }
@@ -494,6 +652,9 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         G.drow = (int32_t* const*)p; p += al256(64 * 8);
         G.prow = (int32_t* const*)p; p += al256(64 * 8);
         p += al256(64 * 4);
+        G.k = (uint32_t)gq.size();
+        G.PS = (uint32_t*)p; p += al256((size_t)n * G.k * 4);
+        G.DS = (uint32_t*)p; p += al256((size_t)n * G.k * 4);
         for (size_t j = 0; j < gq.size(); ++j) {
             hsrc[(size_t)i * 64 + j] = (uint32_t)qs[gq[j]].src;
             rowsD[(size_t)i * 64 + j] = qs[gq[j]].dist;
@@ -547,6 +708,12 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         if ((int64_t)r > maxn + 2) return set_error(GBGPU_E_HIP, "batched BFS did not terminate");
         K = std::min(K * 2, 512);
     }
+    for (int i = 0; i < NG; ++i) {
+        const int tg = (int)std::min<int64_t>(std::max<int64_t>((hg[i].n + 63) / 64, 1), 8192);
+        hipLaunchKernelGGL(ms_transpose_kernel, dim3(tg), dim3(kBlock), 0, stream, dgroups, i);
+    }
+    GB_HIP(hipGetLastError());
+    GB_HIP(hipStreamSynchronize(stream));
     *rounds_out = std::max<int>(*rounds_out, (int)r);
     return GBGPU_OK;
 }

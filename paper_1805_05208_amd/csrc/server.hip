@@ -37,7 +37,7 @@ int wbfs_ws_host_init(WbfsWs* w);
 WbfsWs* wbfs_ws_new();
 int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* parent,
                 const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool* overflow);
-size_t ms_query_bytes(int64_t n);
+size_t ms_query_bytes(int64_t n, int64_t k);
 size_t ms_pin_bytes();
 int run_ms_group_mem(const std::vector<MsQuery>& qs, void* mem, void* pin, const gbgpu_opts& o,
                      hipStream_t stream, int* rounds);
@@ -166,21 +166,26 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
                 if (head.q.kind == GBGPU_QUERY_BFS)
                     for (auto& p : sv->pending)
                         if (p.q.kind == GBGPU_QUERY_BFS && p.q.graph_id == gid && nsame < 64) ++nsame;
-                // admit the batch of same-graph BFS queries if it fits, else
-                // the oldest query alone if it fits, else wait for memory
-                const size_t bb = ms_query_bytes(g->n);
-                if (nsame > 1 && sv->alloc.alloc(bb, &off)) {
-                    bytes = bb;
-                    for (auto it = sv->pending.begin(); it != sv->pending.end() && (int)job.size() < 64;) {
-                        if (it->q.kind == GBGPU_QUERY_BFS && it->q.graph_id == gid) {
-                            job.push_back(*it);
-                            it = sv->pending.erase(it);
-                        } else {
-                            ++it;
+                // admit the largest batch of same-graph BFS queries that fits
+                // (halving from up to 64), else the oldest query alone, else
+                // wait for memory
+                bool taken = false;
+                for (int kb = nsame; kb > 1 && !taken; kb /= 2) {
+                    const size_t bb = ms_query_bytes(g->n, kb);
+                    if (sv->alloc.alloc(bb, &off)) {
+                        bytes = bb;
+                        for (auto it = sv->pending.begin(); it != sv->pending.end() && (int)job.size() < kb;) {
+                            if (it->q.kind == GBGPU_QUERY_BFS && it->q.graph_id == gid) {
+                                job.push_back(*it);
+                                it = sv->pending.erase(it);
+                            } else {
+                                ++it;
+                            }
                         }
+                        taken = true;
                     }
-                    break;
                 }
+                if (taken) break;
                 const size_t nb = query_footprint(g, head.q.kind, head.cap, sv->opts);
                 if (sv->alloc.alloc(nb, &off)) {
                     bytes = nb;

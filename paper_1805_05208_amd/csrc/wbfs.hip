@@ -32,6 +32,14 @@
 //            smallest non-empty slot after the previous bucket), resets the
 //            previous slot, and relaxes bucket b.  The host only checks a done
 //            flag every few hundred launches.
+//   dense    edgeMapData's dense form for a heavy bucket (entries + their
+//            degrees > m / tau): the launch that finds b only marks b's live
+//            vertices in a bucket bitmap (and the settled bitmap); the next
+//            launch pulls: every unsettled vertex v scans its whole list and
+//            takes min over u in bucket b of ((b + w(u,v)) << 32 | u), which is
+//            the same value the pushes of bucket b would leave in key[v].  The
+//            handover between the two launches goes through control words on
+//            the device, so the host still launches blindly.
 
 #include "common.h"
 #include "emit.h"
@@ -50,7 +58,10 @@ struct WbfsWs {
     uint32_t* Qs = nullptr;
     uint32_t* Ps = nullptr;
     unsigned long long* sc = nullptr;
-    uint32_t* ctl = nullptr;   // [0..1] bucket of step j (j & 1), [2] done, [3] overflow
+    uint32_t* S = nullptr;     // settled bitmap
+    uint32_t* Fb = nullptr;    // two bucket bitmaps for dense steps
+    uint32_t* ctl = nullptr;   // [0..1] bucket of step j (j & 1), [2] done, [3] overflow,
+                               // [4..5] step state left by launch j (j & 1)
     uint32_t* log = nullptr;   // kWLogCap * 4
     uint32_t* host_ctl = nullptr;
     void* block = nullptr;     // owned device block (NULL when borrowed)
@@ -87,7 +98,8 @@ static size_t wal(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t wbfs_bytes(int64_t n, uint32_t NB, uint32_t C) {
     return wal((size_t)n * 8) + 2 * wal((size_t)NB * C * 4) +
-           wal((size_t)NB * 8 * kSpreadStride) + wal(64) + wal((size_t)kWLogCap * 16);
+           wal((size_t)NB * 8 * kSpreadStride) + wal(64) + wal((size_t)kWLogCap * 16) +
+           3 * wal((size_t)((n + 63) / 64) * 8);
 }
 
 void wbfs_ws_attach(WbfsWs* w, void* mem, int64_t n, uint32_t NB, uint32_t C) {
@@ -101,7 +113,9 @@ void wbfs_ws_attach(WbfsWs* w, void* mem, int64_t n, uint32_t NB, uint32_t C) {
     w->Ps = (uint32_t*)p; p += wal((size_t)NB * C * 4);
     w->sc = (unsigned long long*)p; p += wal((size_t)NB * 8 * kSpreadStride);
     w->ctl = (uint32_t*)p; p += wal(64);
-    w->log = (uint32_t*)p;
+    w->log = (uint32_t*)p; p += wal((size_t)kWLogCap * 16);
+    w->S = (uint32_t*)p; p += wal((size_t)((n + 63) / 64) * 8);
+    w->Fb = (uint32_t*)p;  // two bitmaps of (n + 63) / 64 * 2 words, each 256-aligned
 }
 
 int wbfs_ws_host_init(WbfsWs* w) {
@@ -144,18 +158,41 @@ struct WbfsArgs {
     uint32_t* Qs;
     uint32_t* Ps;
     unsigned long long* sc;
+    uint32_t* S;
+    uint32_t* Fb;            // bucket bitmap p at Fb + p * fb_stride
     uint32_t* ctl;
     uint32_t* log;
+    const uint4* plan;       // dense-scan work items (runs and hub pieces)
     int64_t n;
     uint32_t NB;
     uint32_t C;
     uint32_t chunk_cap;
+    uint32_t nw32;           // words of one bitmap that cover n vertices
+    uint32_t fb_stride;
+    uint32_t nplan;
+    uint32_t dense_mode;     // 0 by threshold, 1 never, 2 always, 3 odd buckets
+    unsigned long long dense_thresh;
 };
+
+// Step state a launch leaves for the next one (ctl[4 + (j & 1)]).
+constexpr uint32_t kStPull = 1u;      // next launch pulls bucket ctl[j & 1] ...
+constexpr uint32_t kStPullPar = 2u;   // ... with bucket bitmap 1 (else 0)
+constexpr uint32_t kStClear = 4u;     // next launch zeroes a bucket bitmap ...
+constexpr uint32_t kStClearPar = 8u;  // ... bitmap 1 (else 0)
+constexpr uint32_t kStNextPar = 16u;  // the next dense step uses bitmap 1 (else 0)
+
+// Step kinds recorded in the log.
+constexpr uint32_t kModePush = 0u, kModeMark = 1u, kModePull = 2u;
 
 __global__ __launch_bounds__(kBlock) void wbfs_init_kernel(WbfsArgs a, uint32_t src) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = tid; v < a.n; v += stride) a.key[v] = v == src ? (unsigned long long)src : ~0ull;
+    for (int64_t i = tid; i < (a.n + 31) / 32; i += stride) {
+        a.S[i] = 0u;
+        a.Fb[i] = 0u;
+        a.Fb[a.fb_stride + i] = 0u;
+    }
     for (int64_t i = tid; i < a.NB; i += stride)
         a.sc[i * kSpreadStride] = i == 0 ? ((1ull << 32) | a.deg[src]) : 0ull;
     if (tid == 0) {
@@ -165,6 +202,8 @@ __global__ __launch_bounds__(kBlock) void wbfs_init_kernel(WbfsArgs a, uint32_t 
         a.ctl[1] = kStart;
         a.ctl[2] = 0;
         a.ctl[3] = 0;
+        a.ctl[4] = 0;
+        a.ctl[5] = 0;
     }
     for (int64_t i = tid; i < kWLogCap; i += stride) a.log[4 * i + 1] = 0;
 }
@@ -388,14 +427,20 @@ struct RelaxPolicy {
         return (uint32_t)(a->key[u] >> 32) == b ? 1u : 0u;
     }
 
-    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t live, int64_t e) {
+    // A live entry is settled (weights >= 1).  The lane that relaxes its first
+    // edge records that in the settled bitmap, once per vertex, so that later
+    // relaxations towards it skip the random key read.  Vertices without
+    // edges are never relaxation targets and need no bit.
+    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t live, int64_t e,
+                                         bool first) {
         bool moved = false;
         uint32_t v = 0, nd = 0;
+        if (first && live) atomicOr(&a->S[u >> 5], 1u << (u & 31));
         if (act && live) {
             v = (uint32_t)a->nbr[e];
             nd = b + (uint32_t)a->wt[e];
             const unsigned long long nk = ((unsigned long long)nd << 32) | u;
-            if (nk < a->key[v]) {
+            if (!test_bit(a->S, v) && nk < a->key[v]) {
                 const unsigned long long old = atomicMin(&a->key[v], nk);
                 moved = nd < (uint32_t)(old >> 32);
             }
@@ -406,15 +451,105 @@ struct RelaxPolicy {
     __device__ __forceinline__ void window_done() {}
 };
 
+// Dense step, pull side: candidates of the run vertex v from its in-bucket
+// neighbours, folded into the wavefront's per-vertex minimum in LDS.
+struct PullMinPolicy {
+    const WbfsArgs* a;
+    const uint32_t* F;  // bucket bitmap
+    uint32_t b;
+    unsigned long long* smin;
+    uint32_t vb;        // first vertex of the run (slot = v - vb)
+    static constexpr bool kSkipDead = false;
+
+    __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
+
+    __device__ __forceinline__ void edge(bool act, uint32_t v, uint32_t, int64_t e, bool) {
+        if (act) {
+            const uint32_t u = (uint32_t)a->nbr[e];
+            if (test_bit(F, u)) {
+                const unsigned long long c =
+                    ((unsigned long long)(b + (uint32_t)a->wt[e]) << 32) | u;
+                atomicMin(&smin[v - vb], c);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void window_done() {}
+};
+
+// One dense-scan work item: a run of at most 64 consecutive vertices whose
+// lists hold at most 1024 edges together, or a piece of at most 1024 edges of
+// one high-degree vertex.  Settled vertices are skipped.  Wave-uniform.
+__device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t* F, uint32_t b,
+                                               uint4 it, unsigned long long* smin,
+                                               WgBuckets& q) {
+    const int l = lane_id();
+    bool moved = false;
+    uint32_t v = 0, nd = 0;
+    if (it.z == kPlanHub) {
+        v = it.x + (uint32_t)l;
+        bool valid = v < it.y && !test_bit(a.S, v);
+        const uint32_t dg = valid ? a.deg[v] : 0u;
+        valid = valid && dg > 0u;
+        if (!ballot(valid)) return;
+        const int64_t st = valid ? a.off[v] : 0;
+        smin[l] = ~0ull;
+        wave_lds_sync();
+        PullMinPolicy pol{&a, F, b, smin, it.x};
+        expand_lanes(valid, v, st, dg, pol);
+        wave_lds_sync();
+        const unsigned long long best = smin[l];
+        if (valid && best != ~0ull) {
+            const unsigned long long old = a.key[v];
+            if (best < old) {
+                a.key[v] = best;  // the run owns v: no other writer this step
+                nd = (uint32_t)(best >> 32);
+                moved = nd < (uint32_t)(old >> 32);
+            }
+        }
+    } else {
+        v = it.x;
+        if (test_bit(a.S, v)) return;
+        unsigned long long best = ~0ull;
+        for (uint32_t e = it.z + (uint32_t)l; e < it.w; e += 64) {
+            const uint32_t u = (uint32_t)a.nbr[e];
+            if (test_bit(F, u)) {
+                const unsigned long long c =
+                    ((unsigned long long)(b + (uint32_t)a.wt[e]) << 32) | u;
+                best = c < best ? c : best;
+            }
+        }
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            const unsigned long long o = shfl64(best, l ^ s);
+            best = o < best ? o : best;
+        }
+        if (l == 0 && best != ~0ull && best < a.key[v]) {
+            // several pieces of v may race: atomicMin, and a move only on a
+            // strictly smaller distance
+            const unsigned long long old = atomicMin(&a.key[v], best);
+            nd = (uint32_t)(best >> 32);
+            moved = nd < (uint32_t)(old >> 32);
+        }
+    }
+    wgb_push(q, moved, v, nd, a);
+}
+
 __global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint32_t j) {
     __shared__ WgBuckets q;
+    __shared__ unsigned long long s_min[kRWaves][kWave];
     __shared__ uint32_t s_b;
     const int l = lane_id();
     const uint32_t bprev = a.ctl[(j + 1) & 1u];
+    const uint32_t st = a.ctl[4 + ((j + 1) & 1u)];
+    const bool pull = (st & kStPull) != 0u;
     if (threadIdx.x < 64) {
-        // nextBucket: smallest non-empty slot after the previous bucket
+        // nextBucket: smallest non-empty slot after the previous bucket (or
+        // the previous bucket again when its dense step still has to pull)
         uint32_t b = kDone;
-        if (bprev != kDone) {
+        if (pull) {
+            b = bprev;
+        } else if (bprev != kDone) {
             for (uint32_t k0 = 1; k0 < a.NB; k0 += 64) {
                 const uint32_t k = k0 + (uint32_t)l;
                 const bool ne =
@@ -435,27 +570,75 @@ __global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint3
     const uint32_t b = s_b;
     const uint32_t slot = b & (a.NB - 1);
     const unsigned long long packed = b == kDone ? 0ull : *slot_counter(a, slot);
+    const uint32_t cnt = (uint32_t)(packed >> 32);
+    const uint32_t E = (uint32_t)packed;
+    // every workgroup reads the same (b, cnt, E): a pending pull is decided
+    // by the previous launch, and nothing writes slot b while b is current
+    bool dense = false;
+    if (!pull && b != kDone) {
+        if (a.dense_mode == 0u) dense = (unsigned long long)cnt + E > a.dense_thresh;
+        else if (a.dense_mode == 2u) dense = true;
+        else if (a.dense_mode == 3u) dense = (b & 1u) != 0u;
+    }
+    const uint32_t npar = (st & kStNextPar) ? 1u : 0u;
+    uint32_t mode = kModePush, nst = st & kStNextPar;
+    if (pull) {
+        mode = kModePull;
+        nst = kStClear | ((st & kStPullPar) ? kStClearPar : 0u) | (st & kStNextPar);
+    } else if (dense) {
+        mode = kModeMark;
+        nst = kStPull | (npar ? kStPullPar : 0u) | (npar ? 0u : kStNextPar);
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.ctl[j & 1u] = b;
+        a.ctl[4 + (j & 1u)] = nst;
         if (b == kDone) a.ctl[2] = 1u;
         if (bprev != kStart && bprev != kDone) *slot_counter(a, bprev & (a.NB - 1)) = 0ull;
         if (j < (uint32_t)kWLogCap) {
             a.log[4 * j + 0] = b;
-            a.log[4 * j + 1] = b == kDone ? 0u : (uint32_t)(packed >> 32);
-            a.log[4 * j + 2] = (uint32_t)packed;
-            a.log[4 * j + 3] = 0u;
+            a.log[4 * j + 1] = b == kDone ? 0u : cnt;
+            a.log[4 * j + 2] = E;
+            a.log[4 * j + 3] = mode;
         }
     }
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t gstride = gridDim.x * blockDim.x;
+    if (st & kStClear) {
+        // the pull that read this bitmap ended with the previous launch
+        uint32_t* F = a.Fb + ((st & kStClearPar) ? a.fb_stride : 0u);
+        for (uint32_t i = gtid; i < a.nw32; i += gstride) F[i] = 0u;
+    }
     if (b == kDone) return;
-    const uint32_t cnt = (uint32_t)(packed >> 32);
-    const uint32_t E = (uint32_t)packed;
+    const int wib = threadIdx.x / kWave;
+    if (pull) {
+        const uint32_t* F = a.Fb + ((st & kStPullPar) ? a.fb_stride : 0u);
+        const uint32_t ntiles = (a.nplan + kRWaves - 1) / kRWaves;
+        for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const uint32_t it = tile * kRWaves + (uint32_t)wib;
+            if (it < a.nplan) wbfs_pull_item(a, F, b, a.plan[it], s_min[wib], q);
+            wgb_maybe_flush(q, a, kRWaves * kWave);
+        }
+        wgb_flush(q, a);
+        return;
+    }
     if (cnt > a.C) {
         if (threadIdx.x == 0) a.ctl[3] = 1u;
         return;
     }
     const uint32_t* Q = a.Qs + (size_t)slot * a.C;
+    if (dense) {
+        // mark bucket b's live vertices (they are settled now) for the pull
+        uint32_t* F = a.Fb + (npar ? a.fb_stride : 0u);
+        for (uint32_t i = gtid; i < cnt; i += gstride) {
+            const uint32_t u = Q[i];
+            if ((uint32_t)(a.key[u] >> 32) == b) {
+                atomicOr(&F[u >> 5], 1u << (u & 31));
+                atomicOr(&a.S[u >> 5], 1u << (u & 31));
+            }
+        }
+        return;
+    }
     const uint32_t* P = a.Ps + (size_t)slot * a.C;
-    const int wib = threadIdx.x / kWave;
     const uint32_t nwaves = gridDim.x * kRWaves;
     RelaxPolicy pol{&a, &q, b};
     const uint32_t cap = min(a.chunk_cap, (uint32_t)(kWgCapW / (2 * kRWaves)));
@@ -501,12 +684,21 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
     a.Qs = w->Qs;
     a.Ps = w->Ps;
     a.sc = w->sc;
+    a.S = w->S;
+    a.Fb = w->Fb;
     a.ctl = w->ctl;
     a.log = w->log;
+    a.plan = g->plan;
     a.n = g->n;
     a.NB = w->NB;
     a.C = w->C;
     a.chunk_cap = (uint32_t)o.wave_chunk;
+    a.nw32 = (uint32_t)((g->n + 31) / 32);
+    a.fb_stride = (uint32_t)(wal((size_t)((g->n + 63) / 64) * 8) / 4);
+    a.nplan = g->nplan;
+    a.dense_mode = (uint32_t)(o.force_direction == 1 ? 1 : o.force_direction == 2 ? 2
+                              : o.force_direction == 3 ? 3 : 0);
+    a.dense_thresh = (unsigned long long)g->m / (unsigned long long)std::max(o.tau, 1);
     const int igrid = (int)std::min<int64_t>(std::max<int64_t>((g->n + kBlock - 1) / kBlock, 64), 4096);
     hipLaunchKernelGGL(wbfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, (uint32_t)src);
     GB_HIP(hipGetLastError());
@@ -552,8 +744,12 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
         }
         for (size_t i = 0; i < lg.size() / 4; ++i) {
             if (lg[4 * i] == kDone) break;
+            if (lg[4 * i + 3] == kModePull) {
+                st->pull_rounds++;
+                continue;
+            }
             st->rounds++;
-            st->push_rounds++;
+            if (lg[4 * i + 3] == kModePush) st->push_rounds++;
             st->edges_examined += lg[4 * i + 2];
         }
         st->launches = launches;

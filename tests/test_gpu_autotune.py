@@ -1,0 +1,40 @@
+"""The autotuner on the GPU: tuned options reproduce the oracle exactly."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_05208_amd as m
+    m.lib()
+    return m
+
+
+def test_tuned_bfs_and_wbfs_match_oracle(gb, tmp_path):
+    from paper_1805_05208_amd import autotune
+    g = gg.rmat(14, seed=8).with_weights(14, seed=2)
+    G = gb.Graph.from_csr(g)
+    srcs = [int(s) for s in gg.sources(g, 3, seed=3)]
+    space = {"tau": [10, 40], "pull_light": [8, 32], "grid": [256, 512]}
+    rb = autotune.tune_bfs(G, srcs, reps=2, budget_s=20, passes=1, space=space)
+    rw = autotune.tune_wbfs(G, srcs, reps=1, budget_s=20, passes=1,
+                            space={"wave_chunk": [64, 256], "grid": [128, 512]})
+    assert rb["cost"] <= rb["default_cost"] * 1.05
+    for s in srcs:
+        d, p = gb.bfs(G, s, opts=rb["opts"])
+        od, op = oracle.bfs(g, s)
+        assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op)
+        d, p = gb.wbfs(G, s, opts=rw["opts"])
+        od, op = oracle.wbfs(g, s)
+        assert np.array_equal(gb.as_u32(d), od) and np.array_equal(p.cpu().numpy(), op)
+    path = str(tmp_path / "tuned.json")
+    autotune.save([rb, rw], path)
+    assert autotune.lookup(path, rb["signature"], "bfs") == rb["opts"]

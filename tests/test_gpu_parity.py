@@ -67,6 +67,9 @@ def test_small_graphs_all_sources(gb):
             assert_bfs(gb, g, G, s, tag=g.name)
             if g.m:
                 assert_wbfs(gb, g, G, s, tag=g.name)
+                for force in (2, 3):
+                    assert_wbfs(gb, g, G, s, opts={"force_direction": force},
+                                tag=f"{g.name} wforce{force}")
         G.free()
 
 
@@ -108,6 +111,33 @@ def test_forced_directions_identical(gb, rmat16, force):
     g, G = rmat16
     for s in gg.sources(g, 4, seed=3):
         assert_bfs(gb, g, G, int(s), opts={"force_direction": force}, tag=f"force{force}")
+
+
+@pytest.mark.parametrize("force", [1, 2, 3])
+def test_wbfs_forced_directions_identical(gb, rmat16, force):
+    g, G = rmat16
+    for s in gg.sources(g, 4, seed=3):
+        assert_wbfs(gb, g, G, int(s), opts={"force_direction": force}, tag=f"wforce{force}")
+
+
+def test_wbfs_dense_steps_in_auto_mode(gb, rmat16):
+    """The default threshold sends the heavy buckets of an RMAT graph dense;
+    every dense bucket takes a marking launch followed by a pull launch of
+    the same bucket, and buckets come out in increasing order."""
+    g, G = rmat16
+    s = int(gg.sources(g, 1, seed=3)[0])
+    d, p, st = gb.wbfs(G, s, stats=True)
+    assert st["pull_rounds"] > 0 and st["push_rounds"] > 0
+    lg = G.wbfs_log()
+    kinds = lg[:, 3]
+    assert set(np.unique(kinds)) <= {0, 1, 2}
+    for i in np.nonzero(kinds == 1)[0]:
+        assert kinds[i + 1] == 2 and lg[i + 1, 0] == lg[i, 0]
+    buckets = lg[kinds != 2, 0]
+    assert np.all(np.diff(buckets.astype(np.int64)) > 0)
+    assert st["rounds"] == len(buckets) and st["pull_rounds"] == int((kinds == 2).sum())
+    od, op = oracle.wbfs(g, s)
+    assert np.array_equal(gb.as_u32(d), od) and np.array_equal(p.cpu().numpy(), op)
 
 
 @pytest.mark.parametrize("opts", [
