@@ -116,9 +116,16 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--opts", type=str, default="", help="JSON gbgpu_opts overrides")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--pmc-summary", type=str, default="",
+                    help="print per-kernel averages of a rocprofv3 --pmc csv directory and exit")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
@@ -161,15 +168,14 @@ def main():
         outs.append((dn, p.cpu().numpy(), G.bfs_log()))
     step_edges = sum(half_edges)
 
+    if args.copy_probe:
+        copy_probe(torch)
+
     # --- warmup + timed steps ------------------------------------------------
-    popts = dict(user_opts)
-    popts["profile"] = 1
     for _ in range(args.warmup):
         for s in srcs:
             gb.bfs(G, s, opts=user_opts)
     torch.cuda.synchronize()
-    kernel_ms = 0.0
-    launches = 0
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -177,9 +183,7 @@ def main():
     ev0.record(stream)
     for _ in range(args.steps):
         for s in srcs:
-            _, _, st = gb.bfs(G, s, opts=popts, stats=True)
-            kernel_ms += st["kernel_ms"]
-            launches += st["launches"]
+            gb.bfs(G, s, opts=user_opts)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -188,6 +192,18 @@ def main():
     gteps = step_edges * args.steps / wall / 1e9
     log(f"BFS: {ms_per_step:.3f} ms/step ({len(srcs)} sources), {gteps:.1f} GTEPS, "
         f"event time {gpu_ms / args.steps:.3f} ms/step")
+
+    # --- the same steps again with every batch of round-kernel launches
+    # bracketed by HIP events on the library's stream (its own time) --------
+    popts = dict(user_opts)
+    popts["profile"] = 1
+    kernel_ms = 0.0
+    launches = 0
+    for _ in range(args.steps):
+        for s in srcs:
+            _, _, st = gb.bfs(G, s, opts=popts, stats=True)
+            kernel_ms += st["kernel_ms"]
+            launches += st["launches"]
 
     # --- roofline of the round kernel ---------------------------------------
     keys = edge_keys(g)
@@ -256,6 +272,39 @@ def main():
         "extra": extra,
     }
     print(json.dumps(line), flush=True)
+
+
+COPY_PROBE_BYTES = 1 << 30
+
+
+def copy_probe(torch):
+    """A plain device-to-device copy of 1 GiB (read 1 GiB, write 1 GiB), run
+    three times, whose FETCH_SIZE / WRITE_SIZE readings convert the counters
+    into bytes."""
+    x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+
+
+def pmc_summary(path):
+    """Mean counter value per dispatch, by kernel, from the counter_collection
+    csv files rocprofv3 wrote under `path` (FETCH_SIZE and WRITE_SIZE are in
+    KiB)."""
+    import csv
+    import glob
+    from collections import defaultdict
+    acc = defaultdict(lambda: [0.0, set()])
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                k = (row["Kernel_Name"].split("(")[0][:90], row["Counter_Name"])
+                acc[k][0] += float(row["Counter_Value"])
+                acc[k][1].add(row["Dispatch_Id"])
+    for (kern, ctr), (tot, ids) in sorted(acc.items(), key=lambda kv: -kv[1][0]):
+        print(f"{ctr:12s} dispatches={len(ids):6d} mean={tot / len(ids):14.1f}  {kern}")
 
 
 def timed(fn, reps=3):

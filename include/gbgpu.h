@@ -85,7 +85,9 @@ typedef struct {
     int32_t rounds_per_sync; /* launches issued between host completion checks */
     int32_t profile;         /* 1: time each traversal launch with HIP events   */
     int32_t max_pending;     /* server: pending-queue bound (default 65536)     */
-    int32_t reserved[6];
+    int32_t beta;            /* BFS: after a dense round stay dense while
+                                |U| > n / beta (default 24; negative: off)     */
+    int32_t reserved[5];
 } gbgpu_opts;
 
 /* Per-call statistics (optional out-parameter). */

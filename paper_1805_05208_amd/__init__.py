@@ -46,7 +46,7 @@ class Opts(ctypes.Structure):
         ("grid", ctypes.c_int32), ("bucket_window", ctypes.c_int32),
         ("bucket_capacity", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
         ("profile", ctypes.c_int32), ("max_pending", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("beta", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -239,7 +239,7 @@ def bfs(g: Graph, src: int, dist=None, parent=None, opts=None, stream=None,
     oref, _keep = _opts_ref(opts)
     st = Stats()
     _check(lib().gbgpu_bfs(g.handle, int(src), ctypes.c_void_p(dist.data_ptr()),
-                           ctypes.c_void_p(parent.data_ptr()), oref, ctypes.byref(st),
+                           ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats),
                            _stream_ptr(stream)))
     return (dist, parent, st.as_dict()) if stats else (dist, parent)
 
@@ -253,7 +253,7 @@ def wbfs(g: Graph, src: int, dist=None, parent=None, opts=None, stream=None,
     oref, _keep = _opts_ref(opts)
     st = Stats()
     _check(lib().gbgpu_wbfs(g.handle, int(src), ctypes.c_void_p(dist.data_ptr()),
-                            ctypes.c_void_p(parent.data_ptr()), oref, ctypes.byref(st),
+                            ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats),
                             _stream_ptr(stream)))
     return (dist, parent, st.as_dict()) if stats else (dist, parent)
 
@@ -270,7 +270,7 @@ def bfs_multi(g: Graph, srcs: Sequence[int], dist=None, parent=None, opts=None, 
     st = Stats()
     _check(lib().gbgpu_bfs_multi(g.handle, ctypes.c_void_p(s.ctypes.data), k,
                                  ctypes.c_void_p(dist.data_ptr()),
-                                 ctypes.c_void_p(parent.data_ptr()), oref, ctypes.byref(st),
+                                 ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats),
                                  _stream_ptr(stream)))
     return (dist, parent, st.as_dict()) if stats else (dist, parent)
 
@@ -291,8 +291,14 @@ def bfs_batch(graphs: Sequence[Graph], srcs: Sequence[int], dists=None, parents=
     Pp = (ctypes.c_void_p * nq)(*[t.data_ptr() for t in parents])
     oref, _keep = _opts_ref(opts)
     st = Stats()
-    _check(lib().gbgpu_bfs_batch(H, S, nq, D, Pp, oref, ctypes.byref(st), _stream_ptr(stream)))
+    _check(lib().gbgpu_bfs_batch(H, S, nq, D, Pp, oref, _st_ref(st, stats), _stream_ptr(stream)))
     return (dists, parents, st.as_dict()) if stats else (dists, parents)
+
+
+def _st_ref(st, wanted: bool):
+    """The stats out-parameter, or NULL when the caller does not want stats
+    (the library then skips reading its round log back)."""
+    return ctypes.byref(st) if wanted else None
 
 
 def as_u32(t: torch.Tensor) -> np.ndarray:

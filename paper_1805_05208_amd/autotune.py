@@ -26,6 +26,7 @@ BFS_SPACE = {
     "wave_chunk": [64, 128, 256],
     "grid": [256, 384, 512],
     "rounds_per_sync": [4, 8, 12, 16, 32],
+    "beta": [-1, 8, 24, 64],
 }
 WBFS_SPACE = {
     "wave_chunk": [64, 128, 256],
@@ -37,7 +38,8 @@ MULTI_SPACE = {
     "wave_chunk": [64, 128, 256],
     "grid": [256, 384, 512],
 }
-DEFAULTS = {"tau": 20, "pull_light": 32, "wave_chunk": 256, "grid": 512, "rounds_per_sync": 12}
+DEFAULTS = {"tau": 20, "pull_light": 32, "wave_chunk": 256, "grid": 512, "rounds_per_sync": 12,
+            "beta": 24}
 
 
 def coordinate_descent(space: Dict[str, Sequence[int]], start: Dict[str, int],

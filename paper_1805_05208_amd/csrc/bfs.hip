@@ -128,6 +128,7 @@ struct BfsArgs {
     int64_t n;
     int64_t nwords;
     uint64_t dense_thresh;  // go dense when |U| + sum deg(U) > dense_thresh
+    uint32_t stay_dense;    // after a dense round, stay dense while |U| > stay_dense
     int32_t force_dir;
     int32_t light;
     uint32_t chunk_cap;
@@ -204,11 +205,16 @@ struct PushPolicy {
     __device__ __forceinline__ void window_done() {}
 };
 
+// Direction of round r.  A frontier without a queue (it came out of a dense
+// round) stays dense while it holds more than stay_dense vertices, even when
+// its edges are few: the push would touch one list per frontier vertex,
+// while the pull only revisits the still unvisited vertices.
 __device__ __forceinline__ bool choose_push(const BfsArgs& a, uint32_t r, uint32_t count,
-                                            uint32_t edges) {
+                                            uint32_t edges, bool qvalid) {
     if (a.force_dir == 1) return true;
     if (a.force_dir == 2) return false;
     if (a.force_dir == 3) return (r & 1u) == 0u;
+    if (!qvalid && count > a.stay_dense) return false;
     return (uint64_t)count + edges <= a.dense_thresh;
 }
 
@@ -315,13 +321,26 @@ __device__ __forceinline__ void pull_entries(const BfsArgs& a, uint32_t r, uint3
     }
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
-        if (hit[j] != kNone) {
+        const bool f = hit[j] != kNone;
+        if (f) {
             a.dist[v[j]] = (int32_t)(r + 1);
             a.parent[v[j]] = hit[j];
-            atomicOr(&Fn[v[j] >> 5], 1u << (v[j] & 31));
             found += 1;
             dsum += (uint32_t)(e[j] - s[j]);
         }
+        // the lanes' vertices ascend with the lane index, so lanes sharing a
+        // bitmap word are adjacent: OR their bits towards the first lane of
+        // each run and let that lane alone write the word
+        const uint32_t wd = in[j] ? v[j] >> 5 : 0xFFFFFFFFu;
+        uint32_t bits = f ? 1u << (v[j] & 31) : 0u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t ob = __shfl_down(bits, d, 64);
+            const uint32_t ow = __shfl_down(wd, d, 64);
+            if (l + d < 64 && ow == wd) bits |= ob;
+        }
+        const uint32_t pw = __shfl_up(wd, 1, 64);
+        if (bits && (l == 0 || pw != wd)) atomicOr(&Fn[wd], bits);
     }
 }
 
@@ -357,7 +376,7 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
         return;
     }
     const bool qvalid = qover[rs] == 0;
-    const bool push = choose_push(a, r, count, edges);
+    const bool push = choose_push(a, r, count, edges, qvalid);
 
     uint32_t* Fs[3] = {a.F0, a.F1, a.F2};
     const uint32_t* Fc = Fs[r % 3];
@@ -498,6 +517,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.n = g->n;
     a.nwords = g->nwords;
     a.dense_thresh = (uint64_t)g->m / (uint64_t)o.tau;
+    a.stay_dense = o.beta > 0 ? (uint32_t)(g->n / o.beta) : 0xFFFFFFFFu;
     a.force_dir = o.force_direction;
     a.light = o.pull_light;
     a.chunk_cap = (uint32_t)o.wave_chunk;

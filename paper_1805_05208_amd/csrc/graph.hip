@@ -48,6 +48,7 @@ gbgpu_opts resolve_opts(const gbgpu_opts* o) {
     r.wave_chunk = std::max(64, (r.wave_chunk + 63) & ~63);
     if (r.grid <= 0) r.grid = 512;
     if (r.rounds_per_sync <= 0) r.rounds_per_sync = 12;
+    if (r.beta == 0) r.beta = 24;
     if (r.bucket_window < 0) r.bucket_window = 0;
     if (r.bucket_capacity < 0) r.bucket_capacity = 0;
     return r;

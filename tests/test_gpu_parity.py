@@ -143,6 +143,7 @@ def test_wbfs_dense_steps_in_auto_mode(gb, rmat16):
 @pytest.mark.parametrize("opts", [
     {"wave_chunk": 64}, {"wave_chunk": 256, "grid": 7}, {"grid": 1}, {"grid": 3, "pull_light": 1},
     {"pull_light": 4, "tau": 2}, {"tau": 1000}, {"rounds_per_sync": 1},
+    {"beta": -1}, {"beta": 2, "tau": 4}, {"beta": 100000},
 ])
 def test_tuning_knobs_identical(gb, rmat16, opts):
     g, G = rmat16
