@@ -170,12 +170,18 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch)
-
     # --- warmup + timed steps ------------------------------------------------
+    # profile=1 brackets each BFS's round-kernel launches with two HIP events
+    # on the library's stream; stats come from pinned host memory the kernels
+    # write, so neither adds device work
+    popts = dict(user_opts)
+    popts["profile"] = 1
     for _ in range(args.warmup):
         for s in srcs:
-            gb.bfs(G, s, opts=user_opts)
+            gb.bfs(G, s, opts=popts, stats=True)
     torch.cuda.synchronize()
+    kernel_ms = 0.0
+    launches = 0
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -183,7 +189,9 @@ def main():
     ev0.record(stream)
     for _ in range(args.steps):
         for s in srcs:
-            gb.bfs(G, s, opts=user_opts)
+            _, _, st = gb.bfs(G, s, opts=popts, stats=True)
+            kernel_ms += st["kernel_ms"]
+            launches += st["launches"]
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -191,19 +199,8 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     gteps = step_edges * args.steps / wall / 1e9
     log(f"BFS: {ms_per_step:.3f} ms/step ({len(srcs)} sources), {gteps:.1f} GTEPS, "
-        f"event time {gpu_ms / args.steps:.3f} ms/step")
-
-    # --- the same steps again with every batch of round-kernel launches
-    # bracketed by HIP events on the library's stream (its own time) --------
-    popts = dict(user_opts)
-    popts["profile"] = 1
-    kernel_ms = 0.0
-    launches = 0
-    for _ in range(args.steps):
-        for s in srcs:
-            _, _, st = gb.bfs(G, s, opts=popts, stats=True)
-            kernel_ms += st["kernel_ms"]
-            launches += st["launches"]
+        f"event time {gpu_ms / args.steps:.3f} ms/step, round kernels "
+        f"{kernel_ms / args.steps:.3f} ms/step over {launches // args.steps} launches")
 
     # --- roofline of the round kernel ---------------------------------------
     keys = edge_keys(g)

@@ -82,7 +82,9 @@ typedef struct {
     int32_t bucket_window;   /* wBFS: ring of buckets (power of two >= 2*maxw+1) */
     int32_t bucket_capacity; /* wBFS: entries per bucket (retried larger on
                                 overflow)                                       */
-    int32_t rounds_per_sync; /* launches issued between host completion checks */
+    int32_t rounds_per_sync; /* single-source BFS / wBFS: launches kept queued
+                                ahead of the one the device last reported as
+                                started (default 3)                            */
     int32_t profile;         /* 1: time each traversal launch with HIP events   */
     int32_t max_pending;     /* server: pending-queue bound (default 65536)     */
     int32_t beta;            /* BFS: after a dense round stay dense while

@@ -39,9 +39,10 @@ struct BfsWs {
     uint32_t* F[3] = {nullptr, nullptr, nullptr};
     uint32_t* Q[2] = {nullptr, nullptr};
     uint32_t* P[2] = {nullptr, nullptr};
-    unsigned long long* ctl = nullptr;  // qcnt[4], qover[4] at +4/+8, totals at +64
-    uint32_t* log = nullptr;            // kLogCap * 4
-    unsigned long long* host_ctl = nullptr;  // pinned readback
+    unsigned long long* ctl = nullptr;  // qcnt[4], qover[4] at +4/+8, end reported at +12,
+                                        // totals at +64
+    HostLog hl;                         // progress words + round log (host memory)
+    uint32_t last_rounds = 0;           // rounds of the last BFS on this workspace
     void* block = nullptr;              // owned device block (NULL when borrowed)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -50,7 +51,7 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t bfs_ws_bytes(int64_t n, int64_t nwords) {
     return al256((size_t)nwords * 4) * 4 + al256((size_t)(n + 64) * 4) * 4 +
-           al256((64 + 4 * kSpread * kSpreadStride) * 8) + al256((size_t)kLogCap * 16);
+           al256((64 + 4 * kSpread * kSpreadStride) * 8);
 }
 
 // Points the workspace at `mem` (bfs_ws_bytes(n, nwords) bytes of device
@@ -63,16 +64,14 @@ void bfs_ws_attach(BfsWs* w, void* mem, int64_t n, int64_t nwords) {
     for (int i = 0; i < 3; ++i) { w->F[i] = (uint32_t*)p; p += al256((size_t)nwords * 4); }
     for (int i = 0; i < 2; ++i) { w->Q[i] = (uint32_t*)p; p += al256((size_t)(n + 64) * 4); }
     for (int i = 0; i < 2; ++i) { w->P[i] = (uint32_t*)p; p += al256((size_t)(n + 64) * 4); }
-    w->ctl = (unsigned long long*)p; p += al256((64 + 4 * kSpread * kSpreadStride) * 8);
-    w->log = (uint32_t*)p;
+    w->ctl = (unsigned long long*)p;
 }
 
-// Host-side parts: pinned readback buffer and timing events.
+// Host-side parts: pinned progress / log words and timing events.
 int bfs_ws_host_init(BfsWs* w) {
-    if (hipHostMalloc((void**)&w->host_ctl, kSpread * kSpreadStride * 8, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess)
-        return set_error(GBGPU_E_HIP, "BFS workspace: pinned buffer or event creation failed");
+    GB_TRY(host_log_alloc(&w->hl, kLogCap));
+    if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess)
+        return set_error(GBGPU_E_HIP, "BFS workspace: event creation failed");
     return GBGPU_OK;
 }
 
@@ -81,7 +80,7 @@ BfsWs* bfs_ws_new() { return new BfsWs(); }
 void free_bfs_ws(BfsWs* w) {
     if (!w) return;
     if (w->block) (void)hipFree(w->block);
-    if (w->host_ctl) (void)hipHostFree(w->host_ctl);
+    host_log_free(&w->hl);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
     if (w->ev1) (void)hipEventDestroy(w->ev1);
     delete w;
@@ -122,7 +121,8 @@ struct BfsArgs {
     int32_t* dist;
     uint32_t* parent;
     unsigned long long* ctl;
-    uint32_t* log;
+    uint32_t* prog;         // host progress words (device address)
+    uint32_t* log;          // host round log (device address)
     const uint32_t* nz;     // vertices of nonzero degree
     uint32_t nnz;
     int64_t n;
@@ -160,6 +160,7 @@ __global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint3
         qcnt[0] = (1ull << 32) | src_deg;
         for (int i = 1; i < 4; ++i) qcnt[i] = 0;
         for (int i = 0; i < 4; ++i) qover[i] = 0;
+        a.ctl[12] = 0;  // end not yet reported to the host
     }
     // round totals: 4 slots of kSpread counters; slot 0 holds U_0 = {src}
     unsigned long long* tot = a.ctl + 64;
@@ -372,7 +373,12 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     const uint32_t count = (uint32_t)(packed >> 32);
     const uint32_t edges = (uint32_t)packed;
     if (count == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0 && r < (uint32_t)kLogCap) a.log[4 * r + 1] = 0u;
+        // nothing left: the first launch to find that tells the host (the
+        // launches queued behind it find the same)
+        if (blockIdx.x == 0 && threadIdx.x == 0 && a.ctl[12] == 0ull) {
+            a.ctl[12] = 1ull;
+            host_store(&a.prog[1], r + 1);
+        }
         return;
     }
     const bool qvalid = qover[rs] == 0;
@@ -398,11 +404,14 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     out.qlimit = (a.force_dir == 1 || a.force_dir == 3) ? ~0ull : a.dense_thresh;
     out.tot = tot + (size_t)r1 * kSpread * kSpreadStride;
 
-    if (blockIdx.x == 0 && threadIdx.x == 0 && r < (uint32_t)kLogCap) {
-        a.log[4 * r + 0] = push ? (qvalid ? 1u : 3u) : 2u;
-        a.log[4 * r + 1] = count;
-        a.log[4 * r + 2] = edges;
-        a.log[4 * r + 3] = qvalid ? 1u : 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        host_store(&a.prog[0], r + 1);
+        if (r < (uint32_t)kLogCap) {
+            host_store(&a.log[4 * r + 0], push ? (qvalid ? 1u : 3u) : 2u);
+            host_store(&a.log[4 * r + 1], count);
+            host_store(&a.log[4 * r + 2], edges);
+            host_store(&a.log[4 * r + 3], qvalid ? 1u : 0u);
+        }
     }
 
     if (push) {
@@ -511,7 +520,8 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.dist = dist;
     a.parent = (uint32_t*)parent;
     a.ctl = w->ctl;
-    a.log = w->log;
+    a.prog = w->hl.d;
+    a.log = w->hl.d + kHostLogOff;
     a.nz = g->nz;
     a.nnz = g->nnz;
     a.n = g->n;
@@ -530,45 +540,33 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
                        (uint32_t)src);
     GB_HIP(hipGetLastError());
 
-    int launches = 0;
-    double kms = 0.0;
-    uint32_t r = 0;
-    int K = o.rounds_per_sync;
-    const uint32_t max_rounds = (uint32_t)std::min<int64_t>(g->n + 2, 0x7FFFFFFF);
-    for (;;) {
-        if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
-        for (int i = 0; i < K; ++i) {
-            hipLaunchKernelGGL(bfs_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, a, r + i);
-        }
-        GB_HIP(hipGetLastError());
-        if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
-        launches += K;
-        r += (uint32_t)K;
-        GB_HIP(hipMemcpyAsync(w->host_ctl, w->ctl + 64 + (size_t)(r & 3u) * kSpread * kSpreadStride,
-                              kSpread * kSpreadStride * 8, hipMemcpyDeviceToHost, stream));
-        GB_HIP(hipStreamSynchronize(stream));
+    volatile uint32_t* hp = w->hl.h;
+    hp[0] = 0;
+    hp[1] = 0;
+    if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
+    const int64_t max_rounds = std::min<int64_t>(g->n + 2, 0x7FFFFFFF);
+    int64_t launches = 0;
+    GB_TRY(run_pipeline(
+        hp, stream, o.rounds_per_sync, max_rounds,
+        [&](int64_t r) {
+            hipLaunchKernelGGL(bfs_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, a,
+                               (uint32_t)r);
+        },
+        &launches));
+    if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
+    GB_HIP(hipStreamSynchronize(stream));
+    const uint32_t rounds = hp[1] - 1;
+    w->last_rounds = rounds;
+    if (st) {
+        memset(st, 0, sizeof(*st));
         if (o.profile) {
             float ms = 0.f;
             GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-            kms += ms;
+            st->kernel_ms = ms;
         }
-        unsigned long long t = 0;
-        for (int i = 0; i < kSpread; ++i) t += w->host_ctl[i * kSpreadStride];
-        if ((t >> 32) == 0) break;
-        if (r > max_rounds)
-            return set_error(GBGPU_E_HIP, "BFS did not terminate within n rounds");
-        K = std::min(K * 2, 512);
-    }
-    if (st) {
-        std::vector<uint32_t> lg((size_t)std::min<uint32_t>(r, (uint32_t)kLogCap) * 4);
-        if (!lg.empty()) {
-            GB_HIP(hipMemcpyAsync(lg.data(), w->log, lg.size() * 4, hipMemcpyDeviceToHost, stream));
-            GB_HIP(hipStreamSynchronize(stream));
-        }
-        memset(st, 0, sizeof(*st));
+        const uint32_t* lg = w->hl.h + kHostLogOff;
         int64_t reached = 0, ex = 0;
-        for (size_t i = 0; i < lg.size() / 4; ++i) {
-            if (lg[4 * i + 1] == 0) break;
+        for (uint32_t i = 0; i < std::min<uint32_t>(rounds, (uint32_t)kLogCap); ++i) {
             st->rounds++;
             if (lg[4 * i] == 2) st->pull_rounds++; else st->push_rounds++;
             reached += lg[4 * i + 1];
@@ -576,8 +574,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
         }
         st->reached = reached;
         st->edges_examined = ex;
-        st->launches = launches;
-        st->kernel_ms = kms;
+        st->launches = (int32_t)launches;
         st->wall_ms = now_ms() - t0;
     }
     return GBGPU_OK;
@@ -594,12 +591,9 @@ int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gb
 // the benchmark's byte model.
 int bfs_round_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds) {
     if (!g->bfs) { *nrounds = 0; return GBGPU_OK; }
-    int32_t k = std::min<int32_t>(max_rounds, kLogCap);
-    std::vector<uint32_t> lg((size_t)k * 4);
-    GB_HIP(hipMemcpy(lg.data(), g->bfs->log, lg.size() * 4, hipMemcpyDeviceToHost));
-    int32_t r = 0;
-    while (r < k && lg[4 * r + 1] != 0) ++r;
-    memcpy(out, lg.data(), (size_t)r * 16);
+    const int32_t r = (int32_t)std::min<int64_t>(
+        std::min<int64_t>(max_rounds, kLogCap), g->bfs->last_rounds);
+    memcpy(out, g->bfs->hl.h + kHostLogOff, (size_t)r * 16);
     *nrounds = r;
     return GBGPU_OK;
 }

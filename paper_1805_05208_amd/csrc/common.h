@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -92,6 +93,29 @@ gbgpu_opts resolve_opts(const gbgpu_opts* o);
 int ensure_pull_plan(gbgpu_graph g);
 constexpr uint32_t kPlanCap = 1024;   // max edges of one dense-scan work item
 constexpr uint32_t kPlanHub = 0xFFFFFFFFu;
+
+// Words of coherent pinned host memory that the traversal kernels write with
+// system-scope stores and the host reads directly (no copy commands): the
+// progress words of a launch pipeline and the per-step log.
+//   [0] number of launches that have started
+//   [1] 1 + index of the launch that found nothing left to do (0 before)
+//   [2] overflow flag (weighted BFS buckets)
+//   [kHostLogOff ...] 4 words per step
+struct HostLog {
+    uint32_t* h = nullptr;  // host address
+    uint32_t* d = nullptr;  // device address of the same memory
+};
+constexpr size_t kHostLogOff = 16;
+int host_log_alloc(HostLog* hl, size_t log_steps);
+void host_log_free(HostLog* hl);
+
+// Issues launch(0), launch(1), ... on `stream`, keeping `ahead` launches
+// queued beyond the last one the device has reported as started, until a
+// launch reports that nothing is left (prog[1] != 0).  *issued receives the
+// number of launches issued.  Fails if max_launches would be exceeded or the
+// stream reports an error.
+int run_pipeline(volatile uint32_t* prog, hipStream_t stream, int ahead, int64_t max_launches,
+                 const std::function<void(int64_t)>& launch, int64_t* issued);
 }  // namespace gb
 
 // ---------------------------------------------------------------------------
@@ -111,6 +135,11 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
 
 __device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((long long)mask) - 1; }
 __device__ __forceinline__ int last_lane(uint64_t mask) { return 63 - __clzll((long long)mask); }
+
+// Store into coherent host memory, visible to the host without a copy.
+__device__ __forceinline__ void host_store(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // Orders this wavefront's LDS writes before its later LDS reads.
 __device__ __forceinline__ void wave_lds_sync() {

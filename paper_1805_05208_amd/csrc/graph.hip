@@ -9,6 +9,8 @@
 
 #include <time.h>
 
+#include <thread>
+
 #include "common.h"
 
 namespace gb {
@@ -37,6 +39,67 @@ int64_t now_ns() {
     return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
 }
 
+int host_log_alloc(HostLog* hl, size_t log_steps) {
+    const size_t bytes = (kHostLogOff + 4 * log_steps) * 4;
+    if (hipHostMalloc((void**)&hl->h, bytes, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
+        hl->h = nullptr;
+        return set_error(GBGPU_E_NOMEM, "pinned progress/log buffer of %zu bytes", bytes);
+    }
+    memset(hl->h, 0, bytes);
+    if (hipHostGetDevicePointer((void**)&hl->d, hl->h, 0) != hipSuccess) {
+        host_log_free(hl);
+        return set_error(GBGPU_E_HIP, "no device address for the pinned progress buffer");
+    }
+    return GBGPU_OK;
+}
+
+void host_log_free(HostLog* hl) {
+    if (hl->h) (void)hipHostFree(hl->h);
+    hl->h = hl->d = nullptr;
+}
+
+static inline void cpu_relax() { __builtin_ia32_pause(); }
+
+int run_pipeline(volatile uint32_t* prog, hipStream_t stream, int ahead, int64_t max_launches,
+                 const std::function<void(int64_t)>& launch, int64_t* issued_out) {
+    ahead = std::max(ahead, 1);
+    int64_t issued = 0;
+    auto top_up = [&](int64_t upto) {
+        upto = std::min(upto, max_launches);
+        for (; issued < upto; ++issued) launch(issued);
+    };
+    top_up(ahead);
+    GB_HIP(hipGetLastError());
+    for (uint64_t spin = 1;; ++spin) {
+        if (prog[1]) break;
+        const int64_t started = prog[0];
+        if (issued < started + ahead && issued < max_launches) {
+            top_up(started + ahead);
+            GB_HIP(hipGetLastError());
+            continue;
+        }
+        if ((spin & 255u) == 0) {
+            // the queue may have drained before a progress word arrived, or
+            // the device may have failed
+            const hipError_t e = hipStreamQuery(stream);
+            if (e == hipSuccess) {
+                if (prog[1]) break;
+                if (issued >= max_launches)
+                    return set_error(GBGPU_E_HIP, "traversal did not finish within %lld launches",
+                                     (long long)max_launches);
+                top_up(issued + ahead);
+                GB_HIP(hipGetLastError());
+            } else if (e != hipErrorNotReady) {
+                return set_error(GBGPU_E_HIP, "traversal stream failed: %s", hipGetErrorString(e));
+            }
+        }
+        if ((spin & 4095u) == 0) std::this_thread::yield(); else cpu_relax();
+    }
+    *issued_out = issued;
+    return GBGPU_OK;
+}
+
 gbgpu_opts resolve_opts(const gbgpu_opts* o) {
     gbgpu_opts r;
     memset(&r, 0, sizeof(r));
@@ -47,7 +110,7 @@ gbgpu_opts resolve_opts(const gbgpu_opts* o) {
     if (r.wave_chunk <= 0) r.wave_chunk = 256;
     r.wave_chunk = std::max(64, (r.wave_chunk + 63) & ~63);
     if (r.grid <= 0) r.grid = 512;
-    if (r.rounds_per_sync <= 0) r.rounds_per_sync = 12;
+    if (r.rounds_per_sync <= 0) r.rounds_per_sync = 3;
     if (r.beta == 0) r.beta = 24;
     if (r.bucket_window < 0) r.bucket_window = 0;
     if (r.bucket_capacity < 0) r.bucket_capacity = 0;

@@ -685,7 +685,7 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     for (int i = 0; i < NG; ++i) work += std::max<int64_t>(hg[i].n / 64, 1);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((work + kRWaves - 1) / kRWaves, o.grid));
     uint32_t r = 0;
-    int K = o.rounds_per_sync;
+    int K = 8;  // rounds here take milliseconds: a completion check per batch is cheap
     unsigned long long* hp = (unsigned long long*)pin;
     for (;;) {
         for (int i = 0; i < K; ++i)

@@ -62,8 +62,8 @@ struct WbfsWs {
     uint32_t* Fb = nullptr;    // two bucket bitmaps for dense steps
     uint32_t* ctl = nullptr;   // [0..1] bucket of step j (j & 1), [2] done, [3] overflow,
                                // [4..5] step state left by launch j (j & 1)
-    uint32_t* log = nullptr;   // kWLogCap * 4
-    uint32_t* host_ctl = nullptr;
+    HostLog hl;                // progress words + step log (host memory)
+    uint32_t last_steps = 0;   // step launches of the last run on this workspace
     void* block = nullptr;     // owned device block (NULL when borrowed)
     size_t bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -72,7 +72,7 @@ struct WbfsWs {
 void free_wbfs_ws(WbfsWs* w) {
     if (!w) return;
     if (w->block) (void)hipFree(w->block);
-    if (w->host_ctl) (void)hipHostFree(w->host_ctl);
+    host_log_free(&w->hl);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
     if (w->ev1) (void)hipEventDestroy(w->ev1);
     delete w;
@@ -98,8 +98,7 @@ static size_t wal(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t wbfs_bytes(int64_t n, uint32_t NB, uint32_t C) {
     return wal((size_t)n * 8) + 2 * wal((size_t)NB * C * 4) +
-           wal((size_t)NB * 8 * kSpreadStride) + wal(64) + wal((size_t)kWLogCap * 16) +
-           3 * wal((size_t)((n + 63) / 64) * 8);
+           wal((size_t)NB * 8 * kSpreadStride) + wal(64) + 3 * wal((size_t)((n + 63) / 64) * 8);
 }
 
 void wbfs_ws_attach(WbfsWs* w, void* mem, int64_t n, uint32_t NB, uint32_t C) {
@@ -113,15 +112,14 @@ void wbfs_ws_attach(WbfsWs* w, void* mem, int64_t n, uint32_t NB, uint32_t C) {
     w->Ps = (uint32_t*)p; p += wal((size_t)NB * C * 4);
     w->sc = (unsigned long long*)p; p += wal((size_t)NB * 8 * kSpreadStride);
     w->ctl = (uint32_t*)p; p += wal(64);
-    w->log = (uint32_t*)p; p += wal((size_t)kWLogCap * 16);
     w->S = (uint32_t*)p; p += wal((size_t)((n + 63) / 64) * 8);
     w->Fb = (uint32_t*)p;  // two bitmaps of (n + 63) / 64 * 2 words, each 256-aligned
 }
 
 int wbfs_ws_host_init(WbfsWs* w) {
-    if (hipHostMalloc((void**)&w->host_ctl, 64, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess)
-        return set_error(GBGPU_E_HIP, "wBFS workspace: pinned buffer or event creation failed");
+    GB_TRY(host_log_alloc(&w->hl, kWLogCap));
+    if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess)
+        return set_error(GBGPU_E_HIP, "wBFS workspace: event creation failed");
     return GBGPU_OK;
 }
 
@@ -161,7 +159,8 @@ struct WbfsArgs {
     uint32_t* S;
     uint32_t* Fb;            // bucket bitmap p at Fb + p * fb_stride
     uint32_t* ctl;
-    uint32_t* log;
+    uint32_t* prog;          // host progress words (device address)
+    uint32_t* log;           // host step log (device address)
     const uint4* plan;       // dense-scan work items (runs and hub pieces)
     int64_t n;
     uint32_t NB;
@@ -205,7 +204,6 @@ __global__ __launch_bounds__(kBlock) void wbfs_init_kernel(WbfsArgs a, uint32_t 
         a.ctl[4] = 0;
         a.ctl[5] = 0;
     }
-    for (int64_t i = tid; i < kWLogCap; i += stride) a.log[4 * i + 1] = 0;
 }
 
 // Workgroup staging of moved vertices: (vertex, new distance).  At the end of
@@ -542,14 +540,15 @@ __global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint3
     const int l = lane_id();
     const uint32_t bprev = a.ctl[(j + 1) & 1u];
     const uint32_t st = a.ctl[4 + ((j + 1) & 1u)];
-    const bool pull = (st & kStPull) != 0u;
+    const bool over = a.ctl[3] != 0u;  // a bucket overflowed: the run is void
+    const bool pull = (st & kStPull) != 0u && !over;
     if (threadIdx.x < 64) {
         // nextBucket: smallest non-empty slot after the previous bucket (or
         // the previous bucket again when its dense step still has to pull)
         uint32_t b = kDone;
         if (pull) {
             b = bprev;
-        } else if (bprev != kDone) {
+        } else if (bprev != kDone && !over) {
             for (uint32_t k0 = 1; k0 < a.NB; k0 += 64) {
                 const uint32_t k = k0 + (uint32_t)l;
                 const bool ne =
@@ -592,13 +591,21 @@ __global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint3
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.ctl[j & 1u] = b;
         a.ctl[4 + (j & 1u)] = nst;
-        if (b == kDone) a.ctl[2] = 1u;
         if (bprev != kStart && bprev != kDone) *slot_counter(a, bprev & (a.NB - 1)) = 0ull;
-        if (j < (uint32_t)kWLogCap) {
-            a.log[4 * j + 0] = b;
-            a.log[4 * j + 1] = b == kDone ? 0u : cnt;
-            a.log[4 * j + 2] = E;
-            a.log[4 * j + 3] = mode;
+        if (b == kDone) {
+            a.ctl[2] = 1u;
+            if (bprev != kDone) {  // the first launch to find nothing reports it
+                host_store(&a.prog[2], over ? 1u : 0u);
+                host_store(&a.prog[1], j + 1);
+            }
+        } else {
+            host_store(&a.prog[0], j + 1);
+            if (j < (uint32_t)kWLogCap) {
+                host_store(&a.log[4 * j + 0], b);
+                host_store(&a.log[4 * j + 1], cnt);
+                host_store(&a.log[4 * j + 2], E);
+                host_store(&a.log[4 * j + 3], mode);
+            }
         }
     }
     const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -687,7 +694,8 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
     a.S = w->S;
     a.Fb = w->Fb;
     a.ctl = w->ctl;
-    a.log = w->log;
+    a.prog = w->hl.d;
+    a.log = w->hl.d + kHostLogOff;
     a.plan = g->plan;
     a.n = g->n;
     a.NB = w->NB;
@@ -704,46 +712,43 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
     GB_HIP(hipGetLastError());
     const int64_t work = std::max<int64_t>(1, g->m / 4096);
     const int grid = (int)std::min<int64_t>(work, o.grid);
-    uint32_t j = 0;
-    int launches = 0;
-    double kms = 0.0;
-    int K = std::max(16, o.rounds_per_sync);
     *overflow = false;
-    for (;;) {
-        if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
-        for (int i = 0; i < K; ++i)
-            hipLaunchKernelGGL(wbfs_step_kernel, dim3(grid), dim3(kRBlock), 0, stream, a, j + i);
-        GB_HIP(hipGetLastError());
-        if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
-        j += (uint32_t)K;
-        launches += K;
-        GB_HIP(hipMemcpyAsync(w->host_ctl, w->ctl, 16, hipMemcpyDeviceToHost, stream));
-        GB_HIP(hipStreamSynchronize(stream));
-        if (o.profile) {
-            float ms = 0.f;
-            GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-            kms += ms;
-        }
-        if (w->host_ctl[3]) {
-            *overflow = true;
-            return GBGPU_OK;
-        }
-        if (w->host_ctl[2]) break;
-        K = std::min(K * 2, 1024);
-    }
+    volatile uint32_t* hp = w->hl.h;
+    hp[0] = 0;
+    hp[1] = 0;
+    hp[2] = 0;
+    if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
+    // at most one bucket per distinct distance, two launches per dense bucket
+    const int64_t max_launches = 2 * g->n + 4;
+    int64_t launches = 0;
+    GB_TRY(run_pipeline(
+        hp, stream, o.rounds_per_sync, max_launches,
+        [&](int64_t jj) {
+            hipLaunchKernelGGL(wbfs_step_kernel, dim3(grid), dim3(kRBlock), 0, stream, a,
+                               (uint32_t)jj);
+        },
+        &launches));
+    if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
+    // (after an overflow the outputs are rewritten by the rerun)
     hipLaunchKernelGGL(wbfs_finalize_kernel, dim3(igrid), dim3(kBlock), 0, stream, w->key, g->n,
                        dist, parent);
     GB_HIP(hipGetLastError());
     GB_HIP(hipStreamSynchronize(stream));
+    const uint32_t steps = hp[1] - 1;
+    w->last_steps = steps;
+    if (hp[2]) {
+        *overflow = true;
+        return GBGPU_OK;
+    }
     if (st) {
         memset(st, 0, sizeof(*st));
-        std::vector<uint32_t> lg((size_t)std::min<uint32_t>(j, (uint32_t)kWLogCap) * 4);
-        if (!lg.empty()) {
-            GB_HIP(hipMemcpyAsync(lg.data(), w->log, lg.size() * 4, hipMemcpyDeviceToHost, stream));
-            GB_HIP(hipStreamSynchronize(stream));
+        if (o.profile) {
+            float ms = 0.f;
+            GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+            st->kernel_ms = ms;
         }
-        for (size_t i = 0; i < lg.size() / 4; ++i) {
-            if (lg[4 * i] == kDone) break;
+        const uint32_t* lg = w->hl.h + kHostLogOff;
+        for (uint32_t i = 0; i < std::min<uint32_t>(steps, (uint32_t)kWLogCap); ++i) {
             if (lg[4 * i + 3] == kModePull) {
                 st->pull_rounds++;
                 continue;
@@ -752,8 +757,7 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
             if (lg[4 * i + 3] == kModePush) st->push_rounds++;
             st->edges_examined += lg[4 * i + 2];
         }
-        st->launches = launches;
-        st->kernel_ms = kms;
+        st->launches = (int32_t)launches;
         st->wall_ms = now_ms() - t0;
     }
     return GBGPU_OK;
@@ -786,12 +790,9 @@ int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const 
 
 int wbfs_step_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps) {
     if (!g->wbfs) { *nsteps = 0; return GBGPU_OK; }
-    int32_t k = std::min<int32_t>(max_steps, kWLogCap);
-    std::vector<uint32_t> lg((size_t)k * 4);
-    GB_HIP(hipMemcpy(lg.data(), g->wbfs->log, lg.size() * 4, hipMemcpyDeviceToHost));
-    int32_t r = 0;
-    while (r < k && lg[4 * r] != kDone && lg[4 * r + 1] != 0) ++r;
-    memcpy(out, lg.data(), (size_t)r * 16);
+    const int32_t r = (int32_t)std::min<int64_t>(
+        std::min<int64_t>(max_steps, kWLogCap), g->wbfs->last_steps);
+    memcpy(out, g->wbfs->hl.h + kHostLogOff, (size_t)r * 16);
     *nsteps = r;
     return GBGPU_OK;
 }

@@ -172,6 +172,34 @@ def test_repeat_runs_identical(gb, rmat16):
         assert np.array_equal(w, w0) and np.array_equal(q, q0)
 
 
+@pytest.mark.parametrize("ahead", [1, 3, 8])
+def test_round_log_and_stats(gb, rmat16, ahead):
+    """The round log holds one entry per non-empty frontier of this call (a
+    run with fewer rounds after a longer one must not show stale entries),
+    whatever the launch look-ahead."""
+    g, G = rmat16
+    INF = 2**31 - 1
+    cyc = gg.cycle(40).with_weights(6, seed=4)
+    C = gb.Graph.from_csr(cyc)
+    for GG, gg_, s in ((G, g, int(gg.sources(g, 1, seed=3)[0])), (C, cyc, 0),
+                       (G, g, int(gg.sources(g, 2, seed=5)[1]))):
+        d, p, st = gb.bfs(GG, s, opts={"rounds_per_sync": ahead}, stats=True)
+        od, _ = oracle.bfs(gg_, s)
+        assert st["rounds"] == int(od[od != INF].max()) + 1
+        lg = GG.bfs_log()
+        assert len(lg) == st["rounds"]
+        assert int(lg[:, 1].astype(np.int64).sum()) == int((od != INF).sum()) == st["reached"]
+        assert st["launches"] >= st["rounds"] + 1
+        w, q, sw = gb.wbfs(GG, s, opts={"rounds_per_sync": ahead}, stats=True)
+        ow, _ = oracle.wbfs(gg_, s)
+        wl = GG.wbfs_log()
+        assert len(wl) == sw["rounds"] + sw["pull_rounds"]
+        assert len(np.unique(wl[:, 0])) == sw["rounds"]
+        assert np.all(np.diff(wl[wl[:, 3] != 2, 0].astype(np.int64)) > 0)
+        # buckets holding only stale entries are extracted too
+        assert int(wl[:, 0].max()) >= int(ow[ow != 0xFFFFFFFF].max())
+
+
 def test_unit_weights_equal_bfs(gb):
     g = gg.rmat(13, seed=4)
     g.weights = np.ones(g.m, dtype=np.int32)
