@@ -108,7 +108,7 @@ typedef struct {
 
 /* Register a CSR graph that already lives in device memory.
  *   n          number of vertices, 0 < n < 2^31
- *   m          number of stored (directed) entries, 0 <= m < 2^32
+ *   m          number of stored (directed) entries, 0 <= m <= 2^32 - 256
  *   offsets    dev int64[n+1], offsets[0] = 0, offsets[n] = m, non-decreasing
  *   neighbors  dev int32[m], each list sorted strictly ascending (no
  *              duplicates), no self loops, ids in [0, n)

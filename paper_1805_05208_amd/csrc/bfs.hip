@@ -40,7 +40,7 @@ struct BfsWs {
     uint32_t* Q[2] = {nullptr, nullptr};
     uint32_t* P[2] = {nullptr, nullptr};
     unsigned long long* ctl = nullptr;  // qcnt[4], qover[4] at +4/+8, end reported at +12,
-                                        // totals at +64
+                                        // reached counts at +14/+15, totals at +64
     HostLog hl;                         // progress words + round log (host memory)
     uint32_t last_rounds = 0;           // rounds of the last BFS on this workspace
     void* block = nullptr;              // owned device block (NULL when borrowed)
@@ -125,6 +125,7 @@ struct BfsArgs {
     uint32_t* log;          // host round log (device address)
     const uint32_t* nz;     // vertices of nonzero degree
     uint32_t nnz;
+    uint32_t m32;           // number of stored edges
     int64_t n;
     int64_t nwords;
     uint64_t dense_thresh;  // go dense when |U| + sum deg(U) > dense_thresh
@@ -161,6 +162,8 @@ __global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint3
         for (int i = 1; i < 4; ++i) qcnt[i] = 0;
         for (int i = 0; i < 4; ++i) qover[i] = 0;
         a.ctl[12] = 0;  // end not yet reported to the host
+        a.ctl[14] = 0;  // vertices reached through round r - 1, by parity of r
+        a.ctl[15] = 0;
     }
     // round totals: 4 slots of kSpread counters; slot 0 holds U_0 = {src}
     unsigned long long* tot = a.ctl + 64;
@@ -227,39 +230,59 @@ __device__ __forceinline__ bool choose_push(const BfsArgs& a, uint32_t r, uint32
 // round trip, and the vertices are scanned together so that every lane keeps
 // several independent loads in flight.
 constexpr int kPullG = 2;
+// four neighbours in one load; list starts are only 4-byte aligned
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
-__device__ __forceinline__ void pull_entries(const BfsArgs& a, uint32_t r, uint32_t base,
-                                             const uint32_t* __restrict__ Fc, uint32_t* Fn,
-                                             uint32_t& found, uint32_t& dsum) {
+// Scans kPullG x 64 candidate vertices held by the lanes (v[j] ascending
+// with the lane index for each j; in[j] false for empty slots).  With kCheck
+// the candidates are first tested against V | F_r; without it they are known
+// to be unvisited.
+template <bool kCheck>
+__device__ __forceinline__ void pull_vertices(const BfsArgs& a, uint32_t r,
+                                              const uint32_t (&v)[kPullG], const bool (&in)[kPullG],
+                                              const uint32_t* __restrict__ Fc, uint32_t* Fn,
+                                              uint32_t& found, uint32_t& dsum) {
     const int l = lane_id();
-    uint32_t v[kPullG];
-    bool in[kPullG];
-#pragma unroll
-    for (int j = 0; j < kPullG; ++j) {
-        const uint32_t i = base + (uint32_t)l + 64u * j;
-        in[j] = i < a.nnz;
-        v[j] = in[j] ? a.nz[i] : 0u;
-    }
-    bool unvis[kPullG];
-    int64_t s[kPullG], e[kPullG], k[kPullG], lim[kPullG];
+    // edge indices fit in 32 bits (m < 2^32 - 256), which keeps four
+    // vertices' scan state per lane (position, light limit, list end,
+    // parent) within the register budget; a vertex that is not scanned gets
+    // k = lim = e
+    uint32_t e[kPullG], k[kPullG], lim[kPullG];
     uint32_t hit[kPullG];
+    bool any_unvis = false;
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
-        uint32_t vw = ~0u;
-        s[j] = e[j] = 0;
+        uint32_t vw = 0u;
+        uint32_t s0 = 0, e0 = 0;
         if (in[j]) {
-            vw = a.V[v[j] >> 5] | Fc[v[j] >> 5];
-            s[j] = a.off[v[j]];
-            e[j] = a.off[v[j] + 1];
+            if constexpr (kCheck) vw = a.V[v[j] >> 5] | Fc[v[j] >> 5];
+            s0 = (uint32_t)a.off[v[j]];
+            e0 = (uint32_t)a.off[v[j] + 1];
         }
-        unvis[j] = in[j] && !((vw >> (v[j] & 31)) & 1u);
-        lim[j] = unvis[j] ? min(e[j], s[j] + (int64_t)a.light) : s[j];
-        k[j] = s[j];
+        const bool unvis = in[j] && !((vw >> (v[j] & 31)) & 1u);
+        e[j] = unvis ? e0 : 0u;
+        k[j] = unvis ? s0 : 0u;
+        lim[j] = unvis ? min(e0, s0 + a.light) : 0u;
         hit[j] = kNone;
+        any_unvis |= unvis;
     }
-    if (ballot(unvis[0] || unvis[kPullG - 1]) == 0) return;
+    if (ballot(any_unvis) == 0) return;
+    {
+        // most vertices find their parent at the first neighbour: probe it
+        // alone (one list load and one bit test per vertex)
+        uint32_t u[kPullG];
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j) u[j] = k[j] < lim[j] ? (uint32_t)a.nbr[k[j]] : kNone;
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j) {
+            if (u[j] != kNone) {
+                if (test_bit(Fc, u[j])) hit[j] = u[j];
+                k[j] += 1;
+            }
+        }
+    }
     // light phase: lanes scan up to `light` neighbours of each of their
-    // vertices, four at a time, in ascending order
+    // vertices, four at a time (one 16-byte load), in ascending order
     for (;;) {
         bool act[kPullG];
         bool any_act = false;
@@ -271,20 +294,30 @@ __device__ __forceinline__ void pull_entries(const BfsArgs& a, uint32_t r, uint3
         if (!any_act) break;
         uint32_t u[kPullG][4];
 #pragma unroll
-        for (int j = 0; j < kPullG; ++j)
+        for (int j = 0; j < kPullG; ++j) {
+            if (act[j] && k[j] + 4u <= a.m32) {
+                const u32x4_a4 q4 = *(const u32x4_a4*)(a.nbr + k[j]);
+                u[j][0] = q4.x;
+                u[j][1] = q4.y;
+                u[j][2] = q4.z;
+                u[j][3] = q4.w;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    u[j][i] = (act[j] && k[j] + i < a.m32) ? (uint32_t)a.nbr[k[j] + i] : kNone;
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                u[j][i] = (act[j] && k[j] + i < lim[j]) ? (uint32_t)a.nbr[k[j] + i] : kNone;
-        bool h[kPullG][4];
-#pragma unroll
-        for (int j = 0; j < kPullG; ++j)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h[j][i] = u[j][i] != kNone && test_bit(Fc, u[j][i]);
+                if (!act[j] || k[j] + i >= lim[j]) u[j][i] = kNone;
+        }
 #pragma unroll
         for (int j = 0; j < kPullG; ++j) {
             if (act[j]) {
-                hit[j] = h[j][0] ? u[j][0] : h[j][1] ? u[j][1] : h[j][2] ? u[j][2]
-                       : h[j][3] ? u[j][3] : kNone;
+                uint32_t hj = kNone;
+#pragma unroll
+                for (int i = 3; i >= 0; --i)
+                    if (u[j][i] != kNone && test_bit(Fc, u[j][i])) hj = u[j][i];
+                hit[j] = hj;
                 k[j] += 4;
             }
         }
@@ -293,12 +326,12 @@ __device__ __forceinline__ void pull_entries(const BfsArgs& a, uint32_t r, uint3
     // wavefront, 128 neighbours per step, first hit wins
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
-        uint64_t hm = ballot(unvis[j] && hit[j] == kNone && lim[j] < e[j]);
+        uint64_t hm = ballot(hit[j] == kNone && lim[j] < e[j]);
         while (hm) {
             const int hl = first_lane(hm);
             hm &= hm - 1;
-            const int64_t hs = (int64_t)shfl64((uint64_t)lim[j], hl);
-            const int64_t he = (int64_t)shfl64((uint64_t)e[j], hl);
+            const int64_t hs = (int64_t)__shfl(lim[j], hl, 64);
+            const int64_t he = (int64_t)__shfl(e[j], hl, 64);
             uint32_t fu = kNone;
             for (int64_t b = hs; b < he; b += 128) {
                 const int64_t i0 = b + l, i1 = b + 64 + l;
@@ -327,7 +360,7 @@ __device__ __forceinline__ void pull_entries(const BfsArgs& a, uint32_t r, uint3
             a.dist[v[j]] = (int32_t)(r + 1);
             a.parent[v[j]] = hit[j];
             found += 1;
-            dsum += (uint32_t)(e[j] - s[j]);
+            dsum += a.deg[v[j]];
         }
         // the lanes' vertices ascend with the lane index, so lanes sharing a
         // bitmap word are adjacent: OR their bits towards the first lane of
@@ -342,6 +375,86 @@ __device__ __forceinline__ void pull_entries(const BfsArgs& a, uint32_t r, uint3
         }
         const uint32_t pw = __shfl_up(wd, 1, 64);
         if (bits && (l == 0 || pw != wd)) atomicOr(&Fn[wd], bits);
+    }
+}
+
+// Dense pass over the list of vertices of nonzero degree: every wavefront
+// takes kPullG x 64 consecutive entries at a time (balanced when most of them
+// are still unvisited).
+__device__ __forceinline__ void pull_list(const BfsArgs& a, uint32_t r, uint32_t gwave,
+                                          uint32_t nwaves, const uint32_t* __restrict__ Fc,
+                                          uint32_t* Fn, uint32_t* Fclr, uint32_t& found,
+                                          uint32_t& dsum) {
+    // fold U_r into V (leaves V | F_r unchanged) and clear the bitmap that
+    // round r+1 writes
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwords;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t fw = Fc[w];
+        if (fw) a.V[w] |= fw;
+        Fclr[w] = 0u;
+    }
+    const int l = lane_id();
+    const uint32_t per = 64u * kPullG;
+    for (uint32_t base = gwave * per; base < a.nnz; base += nwaves * per) {
+        uint32_t v[kPullG];
+        bool in[kPullG];
+#pragma unroll
+        for (int j = 0; j < kPullG; ++j) {
+            const uint32_t i = base + (uint32_t)l + 64u * j;
+            in[j] = i < a.nnz;
+            v[j] = in[j] ? a.nz[i] : 0u;
+        }
+        pull_vertices<true>(a, r, v, in, Fc, Fn, found, dsum);
+    }
+}
+
+// Dense pass over the unvisited bitmap ~(V | F_r) (degree-0 vertices are
+// in V from the start): every wavefront takes 64 words (2048 vertex ids) at
+// a time, folds U_r into V and clears round r+1's bitmap for them, and
+// scans the unvisited ids it finds, kPullG x 64 at a time in ascending
+// order.  Cheaper than the list once few vertices remain unvisited.
+__device__ __forceinline__ void pull_bitmap(const BfsArgs& a, uint32_t r, uint32_t gwave,
+                                            uint32_t nwaves, const uint32_t* __restrict__ Fc,
+                                            uint32_t* Fn, uint32_t* Fclr, uint32_t& found,
+                                            uint32_t& dsum) {
+    const int l = lane_id();
+    const int64_t nblk = (a.nwords + 63) / 64;
+    for (int64_t blk = gwave; blk < nblk; blk += nwaves) {
+        const int64_t w = blk * 64 + l;
+        uint32_t x = 0u;
+        if (w < a.nwords) {
+            const uint32_t fw = Fc[w];
+            const uint32_t vw = a.V[w];
+            if (fw) a.V[w] = vw | fw;
+            Fclr[w] = 0u;
+            const int64_t v0 = w * 32;
+            x = ~(vw | fw);
+            if (v0 >= a.n) x = 0u;
+            else if (v0 + 32 > a.n) x &= (1u << (uint32_t)(a.n - v0)) - 1u;
+        }
+        const uint32_t c = (uint32_t)__popc(x);
+        const uint32_t inc = wave_incl_sum(c);
+        const uint32_t total = __shfl(inc, 63, 64);
+        const uint32_t excl = inc - c;
+        for (uint32_t B = 0; B < total; B += 64u * kPullG) {
+            uint32_t v[kPullG];
+            bool in[kPullG];
+#pragma unroll
+            for (int j = 0; j < kPullG; ++j) {
+                const uint32_t idx = B + (uint32_t)l + 64u * j;
+                in[j] = idx < total;
+                int o = 0;
+#pragma unroll
+                for (int s = 32; s >= 1; s >>= 1) {
+                    const uint32_t pv = __shfl(excl, o + s, 64);
+                    if (pv <= idx) o += s;
+                }
+                const uint32_t xo = __shfl(x, o, 64);
+                const uint32_t k = idx - __shfl(excl, o, 64);
+                v[j] = in[j] ? (uint32_t)((blk * 64 + o) * 32) + select_bit(xo, k) : 0u;
+            }
+            pull_vertices<false>(a, r, v, in, Fc, Fn, found, dsum);
+        }
     }
 }
 
@@ -372,6 +485,11 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     }
     const uint32_t count = (uint32_t)(packed >> 32);
     const uint32_t edges = (uint32_t)packed;
+    // vertices of nonzero degree not yet reached after round r: the number
+    // reached through round r-1 was left by the previous launch
+    const unsigned long long reached = a.ctl[14 + ((r + 1) & 1u)] + count;
+    const unsigned long long unvisited = a.nnz > reached ? a.nnz - reached : 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[14 + (r & 1u)] = reached;
     if (count == 0) {
         // nothing left: the first launch to find that tells the host (the
         // launches queued behind it find the same)
@@ -475,20 +593,13 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
         }
         wgq_finish(q, out, true);
     } else {
-        // dense round over the list of vertices of nonzero degree; the
-        // output is the bitmap only.  First fold U_r into V (leaves V | F_r
-        // unchanged) and clear the bitmap that round r+1 writes.
+        // dense round; the output is the bitmap only
         if (blockIdx.x == 0 && threadIdx.x == 0) *out.qover = 1ull;
-        for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwords;
-             w += (int64_t)gridDim.x * blockDim.x) {
-            const uint32_t fw = Fc[w];
-            if (fw) a.V[w] |= fw;
-            Fclr[w] = 0u;
-        }
         uint32_t found = 0, dsum = 0;
-        const uint32_t per = 64u * kPullG;
-        for (uint32_t base = gwave * per; base < a.nnz; base += nwaves * per)
-            pull_entries(a, r, base, Fc, Fn, found, dsum);
+        if (2ull * unvisited >= a.nnz)
+            pull_list(a, r, gwave, nwaves, Fc, Fn, Fclr, found, dsum);
+        else
+            pull_bitmap(a, r, gwave, nwaves, Fc, Fn, Fclr, found, dsum);
         found = wave_sum(found);
         dsum = wave_sum(dsum);
         if (l == 0 && found) {
@@ -524,6 +635,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.log = w->hl.d + kHostLogOff;
     a.nz = g->nz;
     a.nnz = g->nnz;
+    a.m32 = (uint32_t)g->m;
     a.n = g->n;
     a.nwords = g->nwords;
     a.dense_thresh = (uint64_t)g->m / (uint64_t)o.tau;
