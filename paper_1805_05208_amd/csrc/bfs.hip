@@ -123,6 +123,7 @@ struct BfsArgs {
     unsigned long long* ctl;
     uint32_t* prog;         // host progress words (device address)
     uint32_t* log;          // host round log (device address)
+    const uint4* head;      // first four neighbours of each vertex
     const uint32_t* nz;     // vertices of nonzero degree
     uint32_t nnz;
     uint32_t m32;           // number of stored edges
@@ -243,43 +244,52 @@ __device__ __forceinline__ void pull_vertices(const BfsArgs& a, uint32_t r,
                                               const uint32_t* __restrict__ Fc, uint32_t* Fn,
                                               uint32_t& found, uint32_t& dsum) {
     const int l = lane_id();
-    // edge indices fit in 32 bits (m < 2^32 - 256), which keeps four
-    // vertices' scan state per lane (position, light limit, list end,
-    // parent) within the register budget; a vertex that is not scanned gets
-    // k = lim = e
-    uint32_t e[kPullG], k[kPullG], lim[kPullG];
+    // 1. the first four neighbours come from the list-head records (one
+    //    coalesced 16-byte load per vertex); the first alone decides most
+    //    vertices
+    uint4 h4[kPullG];
     uint32_t hit[kPullG];
+    bool unvis[kPullG];
     bool any_unvis = false;
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
         uint32_t vw = 0u;
-        uint32_t s0 = 0, e0 = 0;
-        if (in[j]) {
-            if constexpr (kCheck) vw = a.V[v[j] >> 5] | Fc[v[j] >> 5];
-            s0 = (uint32_t)a.off[v[j]];
-            e0 = (uint32_t)a.off[v[j] + 1];
+        if constexpr (kCheck) {
+            if (in[j]) vw = a.V[v[j] >> 5] | Fc[v[j] >> 5];
         }
-        const bool unvis = in[j] && !((vw >> (v[j] & 31)) & 1u);
-        e[j] = unvis ? e0 : 0u;
-        k[j] = unvis ? s0 : 0u;
-        lim[j] = unvis ? min(e0, s0 + a.light) : 0u;
+        unvis[j] = in[j] && !((vw >> (v[j] & 31)) & 1u);
+        h4[j] = unvis[j] ? a.head[v[j]] : make_uint4(kNone, kNone, kNone, kNone);
         hit[j] = kNone;
-        any_unvis |= unvis;
+        any_unvis |= unvis[j];
     }
     if (ballot(any_unvis) == 0) return;
-    {
-        // most vertices find their parent at the first neighbour: probe it
-        // alone (one list load and one bit test per vertex)
-        uint32_t u[kPullG];
 #pragma unroll
-        for (int j = 0; j < kPullG; ++j) u[j] = k[j] < lim[j] ? (uint32_t)a.nbr[k[j]] : kNone;
+    for (int j = 0; j < kPullG; ++j)
+        if (h4[j].x != kNone && test_bit(Fc, h4[j].x)) hit[j] = h4[j].x;
 #pragma unroll
-        for (int j = 0; j < kPullG; ++j) {
-            if (u[j] != kNone) {
-                if (test_bit(Fc, u[j])) hit[j] = u[j];
-                k[j] += 1;
-            }
+    for (int j = 0; j < kPullG; ++j) {
+        if (hit[j] == kNone && h4[j].y != kNone) {
+            const bool b1 = test_bit(Fc, h4[j].y);
+            const bool b2 = h4[j].z != kNone && test_bit(Fc, h4[j].z);
+            const bool b3 = h4[j].w != kNone && test_bit(Fc, h4[j].w);
+            hit[j] = b1 ? h4[j].y : b2 ? h4[j].z : b3 ? h4[j].w : kNone;
         }
+    }
+    // 2. vertices with more than four neighbours and no hit yet continue in
+    //    the list itself.  Edge indices fit in 32 bits (m < 2^32 - 256); a
+    //    vertex that does not continue gets k = lim = e.
+    uint32_t e[kPullG], k[kPullG], lim[kPullG];
+#pragma unroll
+    for (int j = 0; j < kPullG; ++j) {
+        const bool more = unvis[j] && hit[j] == kNone && h4[j].w != kNone;
+        uint32_t s0 = 0, e0 = 0;
+        if (more) {
+            s0 = (uint32_t)a.off[v[j]] + 4u;
+            e0 = (uint32_t)a.off[v[j] + 1];
+        }
+        e[j] = more ? e0 : 0u;
+        k[j] = more ? s0 : 0u;
+        lim[j] = more ? min(e0, s0 + a.light) : 0u;
     }
     // light phase: lanes scan up to `light` neighbours of each of their
     // vertices, four at a time (one 16-byte load), in ascending order
@@ -633,6 +643,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.ctl = w->ctl;
     a.prog = w->hl.d;
     a.log = w->hl.d + kHostLogOff;
+    a.head = g->head;
     a.nz = g->nz;
     a.nnz = g->nnz;
     a.m32 = (uint32_t)g->m;

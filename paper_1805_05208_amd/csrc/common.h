@@ -62,6 +62,7 @@ struct gbgpu_graph_s {
     int64_t nwords = 0;          // bitmap words, padded to a multiple of 2 (64 vertices)
     uint32_t* deg = nullptr;     // owned: degree of each vertex
     uint32_t* zmask = nullptr;   // owned: bit set for degree-0 vertices and padding
+    uint4* head = nullptr;       // owned: first four neighbours of each vertex (kNone-padded)
     int device = 0;
     int num_cus = 256;
     std::mutex mu;               // serialises calls sharing the workspaces

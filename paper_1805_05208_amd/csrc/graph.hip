@@ -195,11 +195,22 @@ __global__ void max_weight_kernel(const int32_t* w, int64_t m, int32_t* maxw) {
     if (lane_id() == 0 && lm > 0) atomicMax(maxw, lm);
 }
 
-__global__ void degree_kernel(const int64_t* off, int64_t n, int64_t nwords, uint32_t* deg,
-                              uint32_t* zmask) {
+// Degrees, the degree-0 bitmap, and the head of every list: its first four
+// neighbours (kNone-padded) in one 16-byte record, so a dense scan that stops
+// early reads them with one coalesced load instead of one random line of the
+// neighbour array per vertex.
+__global__ void degree_kernel(const int64_t* off, const int32_t* nbr, int64_t n, int64_t nwords,
+                              uint32_t* deg, uint32_t* zmask, uint4* head) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = t; v < n; v += stride) deg[v] = (uint32_t)(off[v + 1] - off[v]);
+    for (int64_t v = t; v < n; v += stride) {
+        const int64_t s0 = off[v];
+        const int64_t d = off[v + 1] - s0;
+        deg[v] = (uint32_t)d;
+        uint32_t h[4];
+        for (int i = 0; i < 4; ++i) h[i] = i < d ? (uint32_t)nbr[s0 + i] : kNone;
+        head[v] = make_uint4(h[0], h[1], h[2], h[3]);
+    }
     for (int64_t w = t; w < nwords; w += stride) {
         uint32_t bits = 0;
         for (int b = 0; b < 32; ++b) {
@@ -324,12 +335,14 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
     auto fail = [&](int st) {
         if (g->deg) (void)hipFree(g->deg);
         if (g->zmask) (void)hipFree(g->zmask);
+        if (g->head) (void)hipFree(g->head);
         if (scratch) (void)hipFree(scratch);
         delete g;
         return st;
     };
     if (hipMalloc(&g->deg, (size_t)n * 4) != hipSuccess ||
         hipMalloc(&g->zmask, (size_t)g->nwords * 4) != hipSuccess ||
+        hipMalloc(&g->head, (size_t)n * sizeof(uint4)) != hipSuccess ||
         hipMalloc(&scratch, 16) != hipSuccess)
         return fail(set_error(GBGPU_E_NOMEM, "graph metadata allocation failed"));
     if (hipMemsetAsync(scratch, 0, 16, s) != hipSuccess)
@@ -368,7 +381,7 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
     g->maxw = weights ? (int32_t)host[1] : 0;
     if (weights && m > 0 && g->maxw < 1) return fail(set_error(GBGPU_E_INVALID, "weight < 1"));
     hipLaunchKernelGGL(degree_kernel, dim3(grid_for(std::max<int64_t>(n, g->nwords))), dim3(kBlock),
-                       0, s, offsets, n, g->nwords, g->deg, g->zmask);
+                       0, s, offsets, neighbors, n, g->nwords, g->deg, g->zmask, g->head);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return fail(set_error(GBGPU_E_HIP, "degree kernel failed"));
     (void)hipFree(scratch);
@@ -390,6 +403,7 @@ int gbgpu_graph_free(gbgpu_graph g) {
         if (g->nz) (void)hipFree(g->nz);
         (void)hipFree(g->deg);
         (void)hipFree(g->zmask);
+        (void)hipFree(g->head);
     }
     delete g;
     return GBGPU_OK;
