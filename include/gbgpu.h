@@ -27,7 +27,11 @@
  *     instance torch tensor data); "host" pointers are ordinary host memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Work is ordered on that stream; the traversal calls return only when
- *     their outputs are complete.
+ *     their outputs are complete in device memory.  gbgpu_bfs may leave a
+ *     few empty traversal launches queued on the stream behind that point;
+ *     they touch only the library's workspace, and later work on the stream
+ *     (or a later call on the same graph, on any stream) is ordered after
+ *     them.
  *   - Graph handles are immutable after load and may be shared between
  *     threads; calls on one handle are serialised internally because they
  *     share its workspace.

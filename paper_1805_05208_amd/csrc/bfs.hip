@@ -45,6 +45,7 @@ struct BfsWs {
     uint32_t last_rounds = 0;           // rounds of the last BFS on this workspace
     void* block = nullptr;              // owned device block (NULL when borrowed)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t done = nullptr;          // after the last launch of the last run
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -70,7 +71,8 @@ void bfs_ws_attach(BfsWs* w, void* mem, int64_t n, int64_t nwords) {
 // Host-side parts: pinned progress / log words and timing events.
 int bfs_ws_host_init(BfsWs* w) {
     GB_TRY(host_log_alloc(&w->hl, kLogCap));
-    if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess)
+    if (hipEventCreate(&w->ev0) != hipSuccess || hipEventCreate(&w->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&w->done, hipEventDisableTiming) != hipSuccess)
         return set_error(GBGPU_E_HIP, "BFS workspace: event creation failed");
     return GBGPU_OK;
 }
@@ -80,6 +82,10 @@ BfsWs* bfs_ws_new() { return new BfsWs(); }
 void free_bfs_ws(BfsWs* w) {
     if (!w) return;
     if (w->block) (void)hipFree(w->block);
+    if (w->done) {
+        (void)hipEventSynchronize(w->done);  // launches of the last run may still be queued
+        (void)hipEventDestroy(w->done);
+    }
     host_log_free(&w->hl);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
     if (w->ev1) (void)hipEventDestroy(w->ev1);
@@ -623,9 +629,14 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     }
 }
 
+// One BFS on workspace w.  The results are complete when this returns; the
+// few launches queued behind the one that found the frontier empty may still
+// be pending unless sync_end is set.  They only touch the workspace, and the
+// next run on it (on any stream) waits for them.
 int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* parent,
-               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream) {
+               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool sync_end) {
     const double t0 = now_ms();
+    GB_HIP(hipStreamWaitEvent(stream, w->done, 0));
     BfsArgs a;
     a.off = g->off;
     a.nbr = g->nbr;
@@ -677,7 +688,11 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
         },
         &launches));
     if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
-    GB_HIP(hipStreamSynchronize(stream));
+    GB_HIP(hipEventRecord(w->done, stream));
+    // every round that wrote results has finished once the device reported
+    // the empty frontier
+    if (sync_end) GB_HIP(hipStreamSynchronize(stream));
+    else if (o.profile) GB_HIP(hipEventSynchronize(w->ev1));
     const uint32_t rounds = hp[1] - 1;
     w->last_rounds = rounds;
     if (st) {
@@ -706,7 +721,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
 int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
             gbgpu_stats* st, hipStream_t stream) {
     GB_TRY(ensure_bfs_ws(g));
-    return run_bfs_ws(g, g->bfs, src, dist, parent, o, st, stream);
+    return run_bfs_ws(g, g->bfs, src, dist, parent, o, st, stream, false);
 }
 
 // Round log of the last BFS on this graph: 4 words per round (direction 1 =

@@ -265,3 +265,23 @@ def test_validation_rejects_malformed_graphs(gb):
     with pytest.raises(gb.GbgpuError):
         gb.Graph(np.array([0, 1, 2]), np.array([1, 0], dtype=np.int32),
                  np.array([0, 0], dtype=np.int32))
+
+
+def test_back_to_back_calls_on_two_streams(gb, rmat16):
+    """A BFS may return with empty launches still queued on its stream; a
+    following call on the same graph from another stream must wait for them
+    (outputs of both equal the oracle)."""
+    g, G = rmat16
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    srcs = [int(x) for x in gg.sources(g, 6, seed=11)]
+    outs = []
+    for i, s in enumerate(srcs):
+        st = s1 if i % 2 == 0 else s2
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        gb.bfs(G, s, dist=d, parent=p, stream=st, opts={"rounds_per_sync": 6})
+        outs.append((s, d, p))
+    torch.cuda.synchronize()
+    for s, d, p in outs:
+        od, op = oracle.bfs(g, s)
+        assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op), s
