@@ -87,8 +87,13 @@ def bfs_bytes(g, keys, dist, parent, rlog):
     v = np.nonzero(reach & (parent != np.arange(n)))[0]
     pos = np.zeros(n, dtype=np.int64)
     pos[v] = parent_positions(g, keys, v, parent)
-    nz = deg > 0
-    total = 0
+    # the rounds scan the vertices of degree >= 2; degree-1 vertices are
+    # attached after the last round (8 B of list entries each, 4 B of their
+    # neighbour's distance, 8 B of outputs when reached)
+    nz = deg >= 2
+    leaves = deg == 1
+    leaf_bytes = 12 * int(leaves.sum()) + 8 * int((leaves & reach).sum())
+    total = leaf_bytes
     per_round = []
     for r, (direction, cnt, edges, _q) in enumerate(rlog):
         cnt_next = rlog[r + 1][1] if r + 1 < len(rlog) else 0

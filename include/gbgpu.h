@@ -98,7 +98,8 @@ typedef struct {
 
 /* Per-call statistics (optional out-parameter). */
 typedef struct {
-    int32_t rounds;          /* BFS rounds / wBFS buckets processed            */
+    int32_t rounds;          /* BFS: depth (largest finite distance + 1);
+                                wBFS: buckets processed                       */
     int32_t push_rounds;     /* rounds run sparse (push)                       */
     int32_t pull_rounds;     /* rounds run dense (pull)                        */
     int32_t launches;        /* traversal kernel launches issued               */
@@ -247,7 +248,10 @@ int gbgpu_query_footprint(gbgpu_graph g, int32_t kind, size_t* bytes);
 /* Per-round log of the last gbgpu_bfs on g, 4 uint32 per round: direction
  * (1 sparse push from the queue, 2 dense pull, 3 sparse push from the
  * bitmap), |U_r|, sum of deg(U_r), whether the sparse queue was available.
- * out holds max_rounds * 4 words (host). */
+ * The rounds run over the vertices of degree >= 2 (and the source); vertices
+ * of degree 1 are attached through their one neighbour after the last round,
+ * so they appear in no |U_r| (and may make the depth one more than the
+ * number of rounds).  out holds max_rounds * 4 words (host). */
 int gbgpu_debug_bfs_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds);
 
 /* Per-launch log of the last gbgpu_wbfs on g, 4 uint32 per step launch:

@@ -130,8 +130,12 @@ struct BfsArgs {
     uint32_t* prog;         // host progress words (device address)
     uint32_t* log;          // host round log (device address)
     const uint4* head;      // first four neighbours of each vertex
-    const uint32_t* nz;     // vertices of nonzero degree
+    const uint32_t* nz;     // vertices of degree >= 2 (the ones dense rounds scan)
     uint32_t nnz;
+    const uint32_t* leaf;   // vertices of degree 1 and their one neighbour
+    const uint32_t* leafnbr;
+    uint32_t nleaf;
+    uint32_t src;
     uint32_t m32;           // number of stored edges
     int64_t n;
     int64_t nwords;
@@ -145,7 +149,7 @@ struct BfsArgs {
 // ---------------------------------------------------------------------------
 // init: dist = INF, parent = -1, V = zero-degree mask, F = {src}, Q = [src]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint32_t* zmask,
+__global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint32_t* pruned,
                                                           uint32_t src) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint3
         a.parent[v] = v == src ? src : kNone;
     }
     for (int64_t w = tid; w < a.nwords; w += stride) {
-        a.V[w] = zmask[w];
+        a.V[w] = pruned[w];
         a.F0[w] = (w == (int64_t)(src >> 5)) ? (1u << (src & 31)) : 0u;
         a.F1[w] = 0u;
         a.F2[w] = 0u;
@@ -168,7 +172,9 @@ __global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint3
         qcnt[0] = (1ull << 32) | src_deg;
         for (int i = 1; i < 4; ++i) qcnt[i] = 0;
         for (int i = 0; i < 4; ++i) qover[i] = 0;
-        a.ctl[12] = 0;  // end not yet reported to the host
+        a.ctl[13] = 0;  // workgroups done with the leaf pass
+        a.ctl[16] = 0;  // leaves reached
+        a.ctl[17] = 0;  // largest leaf distance
         a.ctl[14] = 0;  // vertices reached through round r - 1, by parity of r
         a.ctl[15] = 0;
     }
@@ -229,14 +235,13 @@ __device__ __forceinline__ bool choose_push(const BfsArgs& a, uint32_t r, uint32
     return (uint64_t)count + edges <= a.dense_thresh;
 }
 
-// Dense (pull) processing of kPullG x 64 entries of the list of vertices of
-// nonzero degree by one wavefront (lane l owns entries base + l + 64 j).
-// Each unvisited vertex scans its list in ascending order and stops at the
-// first member of the frontier, which is its parent.  The visited and
-// frontier words and the list bounds of all owned vertices are loaded in one
-// round trip, and the vertices are scanned together so that every lane keeps
-// several independent loads in flight.
-constexpr int kPullG = 2;
+// Dense (pull) processing: each unvisited vertex scans its list in ascending
+// order and stops at the first member of the frontier, which is its parent.
+// A wavefront holds kPullG x 64 candidates at a time (lane l owns candidates
+// l + 64 j).  The rounds are bound by scattered requests in flight per CU,
+// not by registers, so one candidate per lane is the fastest setting (more
+// per lane lengthens every wavefront's slowest chain).
+constexpr int kPullG = 1;
 // four neighbours in one load; list starts are only 4-byte aligned
 typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
@@ -275,10 +280,11 @@ __device__ __forceinline__ void pull_vertices(const BfsArgs& a, uint32_t r,
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
         if (hit[j] == kNone && h4[j].y != kNone) {
-            const bool b1 = test_bit(Fc, h4[j].y);
-            const bool b2 = h4[j].z != kNone && test_bit(Fc, h4[j].z);
-            const bool b3 = h4[j].w != kNone && test_bit(Fc, h4[j].w);
-            hit[j] = b1 ? h4[j].y : b2 ? h4[j].z : b3 ? h4[j].w : kNone;
+            // one bit test at a time: fewer scattered requests, and most of
+            // these vertices stop at the second neighbour
+            if (test_bit(Fc, h4[j].y)) hit[j] = h4[j].y;
+            else if (h4[j].z != kNone && test_bit(Fc, h4[j].z)) hit[j] = h4[j].z;
+            else if (h4[j].w != kNone && test_bit(Fc, h4[j].w)) hit[j] = h4[j].w;
         }
     }
     // 2. vertices with more than four neighbours and no hit yet continue in
@@ -474,9 +480,53 @@ __device__ __forceinline__ void pull_bitmap(const BfsArgs& a, uint32_t r, uint32
     }
 }
 
+// Degree-1 vertices take no part in the rounds (they start in V): such a
+// vertex can only be reached through its one neighbour u and is never the
+// parent of anyone else, so after the last round D[v] = D[u] + 1 and
+// parent[v] = u whenever u was reached.  The last workgroup to finish this
+// pass reports the end of the BFS to the host.
+__device__ __forceinline__ void attach_leaves(const BfsArgs& a, uint32_t r, WgQueue& q) {
+    uint32_t reached = 0, deepest = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.nleaf;
+         i += gridDim.x * blockDim.x) {
+        const uint32_t v = a.leaf[i];
+        const uint32_t u = a.leafnbr[i];
+        const int32_t du = v == a.src ? INT32_MAX : a.dist[u];
+        if (du != INT32_MAX) {
+            a.dist[v] = du + 1;
+            a.parent[v] = u;
+            ++reached;
+            deepest = max(deepest, (uint32_t)du + 1u);
+        }
+    }
+    reached = wave_sum(reached);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) deepest = max(deepest, (uint32_t)__shfl_xor(deepest, d, 64));
+    if (lane_id() == 0 && reached) {
+        atomicAdd(&q.found, reached);
+        atomicMax(&q.fdsum, deepest);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (q.found) {
+            atomicAdd(&a.ctl[16], (unsigned long long)q.found);
+            atomicMax(&a.ctl[17], (unsigned long long)q.fdsum);
+        }
+        __threadfence();
+        const unsigned long long done = atomicAdd(&a.ctl[13], 1ull);
+        if (done == gridDim.x - 1) {
+            __threadfence();
+            host_store(&a.prog[2], (uint32_t)atomicAdd(&a.ctl[16], 0ull));
+            host_store(&a.prog[3], (uint32_t)atomicMax(&a.ctl[17], 0ull));
+            __threadfence_system();
+            host_store(&a.prog[1], r + 1);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32_t r) {
     __shared__ WgQueue q;
-    __shared__ unsigned long long s_tot;
+    __shared__ unsigned long long s_tot, s_prev;
 
     unsigned long long* qcnt = a.ctl + 4;
     unsigned long long* qover = a.ctl + 8;
@@ -485,6 +535,11 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     if (threadIdx.x < kWave) {
         const unsigned long long t = spread_sum(tot + (size_t)rs * kSpread * kSpreadStride);
         if (threadIdx.x == 0) s_tot = t;
+    } else if (threadIdx.x < 2 * kWave) {
+        // round r-1's totals (its slot is next cleared by round r+1)
+        const unsigned long long t =
+            spread_sum(tot + (size_t)((r + 3) & 3u) * kSpread * kSpreadStride);
+        if (threadIdx.x == kWave) s_prev = t;
     }
     wgq_init(q);
     __syncthreads();
@@ -507,12 +562,10 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     const unsigned long long unvisited = a.nnz > reached ? a.nnz - reached : 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[14 + (r & 1u)] = reached;
     if (count == 0) {
-        // nothing left: the first launch to find that tells the host (the
-        // launches queued behind it find the same)
-        if (blockIdx.x == 0 && threadIdx.x == 0 && a.ctl[12] == 0ull) {
-            a.ctl[12] = 1ull;
-            host_store(&a.prog[1], r + 1);
-        }
+        // nothing left.  The first launch to find that (round r-1 still had
+        // vertices) attaches the degree-1 vertices and tells the host; the
+        // launches queued behind it return at once.
+        if ((s_prev >> 32) != 0) attach_leaves(a, r, q);
         return;
     }
     const bool qvalid = qover[rs] == 0;
@@ -655,8 +708,12 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.prog = w->hl.d;
     a.log = w->hl.d + kHostLogOff;
     a.head = g->head;
-    a.nz = g->nz;
-    a.nnz = g->nnz;
+    a.nz = g->core;
+    a.nnz = g->ncore;
+    a.leaf = g->leaf;
+    a.leafnbr = g->leafnbr;
+    a.nleaf = g->nleaf;
+    a.src = (uint32_t)src;
     a.m32 = (uint32_t)g->m;
     a.n = g->n;
     a.nwords = g->nwords;
@@ -670,13 +727,15 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     int grid = (int)std::min<int64_t>(std::max<int64_t>(work, 1), o.grid);
     int igrid = (int)std::min<int64_t>((g->n + kBlock - 1) / kBlock, 4096);
     if (igrid < 1) igrid = 1;
-    hipLaunchKernelGGL(bfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, g->zmask,
+    hipLaunchKernelGGL(bfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, g->pruned,
                        (uint32_t)src);
     GB_HIP(hipGetLastError());
 
     volatile uint32_t* hp = w->hl.h;
     hp[0] = 0;
     hp[1] = 0;
+    hp[2] = 0;
+    hp[3] = 0;
     if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
     const int64_t max_rounds = std::min<int64_t>(g->n + 2, 0x7FFFFFFF);
     int64_t launches = 0;
@@ -710,7 +769,10 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
             reached += lg[4 * i + 1];
             ex += lg[4 * i + 2];
         }
-        st->reached = reached;
+        // attached degree-1 vertices: counted, and one level deeper than the
+        // last round when they hang off its vertices
+        st->reached = reached + hp[2];
+        st->rounds = std::max<int32_t>(st->rounds, (int32_t)hp[3] + 1);
         st->edges_examined = ex;
         st->launches = (int32_t)launches;
         st->wall_ms = now_ms() - t0;

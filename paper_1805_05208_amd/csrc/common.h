@@ -61,7 +61,8 @@ struct gbgpu_graph_s {
     int32_t maxw = 0;
     int64_t nwords = 0;          // bitmap words, padded to a multiple of 2 (64 vertices)
     uint32_t* deg = nullptr;     // owned: degree of each vertex
-    uint32_t* zmask = nullptr;   // owned: bit set for degree-0 vertices and padding
+    uint32_t* pruned = nullptr;  // owned: bit set for vertices of degree 0 or 1 and padding
+                                 // (the BFS rounds never scan them)
     uint4* head = nullptr;       // owned: first four neighbours of each vertex (kNone-padded)
     int device = 0;
     int num_cus = 256;
@@ -69,8 +70,11 @@ struct gbgpu_graph_s {
     std::mutex plan_mu;          // guards the lazily built pull plan
     uint4* plan = nullptr;       // owned: dense-scan work items (see ensure_pull_plan)
     uint32_t nplan = 0;
-    uint32_t* nz = nullptr;      // owned: ids of the vertices of nonzero degree, ascending
-    uint32_t nnz = 0;
+    uint32_t* core = nullptr;    // owned: ids of the vertices of degree >= 2, ascending
+    uint32_t ncore = 0;
+    uint32_t* leaf = nullptr;    // owned: ids of the vertices of degree 1, ascending
+    uint32_t* leafnbr = nullptr; // owned: the one neighbour of each of them
+    uint32_t nleaf = 0;
     gb::BfsWs* bfs = nullptr;
     gb::WbfsWs* wbfs = nullptr;
     gb::MultiWs* multi = nullptr;

@@ -195,12 +195,13 @@ __global__ void max_weight_kernel(const int32_t* w, int64_t m, int32_t* maxw) {
     if (lane_id() == 0 && lm > 0) atomicMax(maxw, lm);
 }
 
-// Degrees, the degree-0 bitmap, and the head of every list: its first four
+// Degrees, the bitmap of vertices of degree <= 1, and the head of every
+// list: its first four
 // neighbours (kNone-padded) in one 16-byte record, so a dense scan that stops
 // early reads them with one coalesced load instead of one random line of the
 // neighbour array per vertex.
 __global__ void degree_kernel(const int64_t* off, const int32_t* nbr, int64_t n, int64_t nwords,
-                              uint32_t* deg, uint32_t* zmask, uint4* head) {
+                              uint32_t* deg, uint32_t* pruned, uint4* head) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = t; v < n; v += stride) {
@@ -215,10 +216,21 @@ __global__ void degree_kernel(const int64_t* off, const int32_t* nbr, int64_t n,
         uint32_t bits = 0;
         for (int b = 0; b < 32; ++b) {
             int64_t v = w * 32 + b;
-            if (v >= n || off[v + 1] == off[v]) bits |= 1u << b;
+            if (v >= n || off[v + 1] - off[v] <= 1) bits |= 1u << b;
         }
-        zmask[w] = bits;
+        pruned[w] = bits;
     }
+}
+
+static int grid_for(int64_t items) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+__global__ void leaf_nbr_kernel(const int64_t* off, const int32_t* nbr, const uint32_t* leaf,
+                                uint32_t nleaf, uint32_t* leafnbr) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nleaf; i += gridDim.x * blockDim.x)
+        leafnbr[i] = (uint32_t)nbr[off[leaf[i]]];
 }
 
 // Dense-scan plan: work items that cover every non-isolated vertex once.
@@ -258,38 +270,64 @@ int ensure_pull_plan(gbgpu_graph g) {
         }
         items.push_back(make_uint4((uint32_t)vb, (uint32_t)i, kPlanHub, 0u));
     }
-    std::vector<uint32_t> nzv;
-    nzv.reserve((size_t)n);
-    for (int64_t v = 0; v < n; ++v)
-        if (off[v + 1] > off[v]) nzv.push_back((uint32_t)v);
-    uint32_t* d_nz = nullptr;
-    if (hipMalloc(&d_nz, std::max<size_t>(nzv.size(), 1) * 4) != hipSuccess)
+    // vertex lists for the BFS: degree >= 2 (scanned by dense rounds) and
+    // degree 1 (attached after the rounds through their one neighbour)
+    std::vector<uint32_t> corev, leafv;
+    corev.reserve((size_t)n);
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t d = off[v + 1] - off[v];
+        if (d >= 2) corev.push_back((uint32_t)v);
+        else if (d == 1) leafv.push_back((uint32_t)v);
+    }
+    uint32_t *d_core = nullptr, *d_leaf = nullptr, *d_leafnbr = nullptr;
+    auto free_lists = [&]() {
+        if (d_core) (void)hipFree(d_core);
+        if (d_leaf) (void)hipFree(d_leaf);
+        if (d_leafnbr) (void)hipFree(d_leafnbr);
+    };
+    if (hipMalloc(&d_core, std::max<size_t>(corev.size(), 1) * 4) != hipSuccess ||
+        hipMalloc(&d_leaf, std::max<size_t>(leafv.size(), 1) * 4) != hipSuccess ||
+        hipMalloc(&d_leafnbr, std::max<size_t>(leafv.size(), 1) * 4) != hipSuccess) {
+        free_lists();
         return set_error(GBGPU_E_NOMEM, "vertex list allocation failed");
-    if (!nzv.empty() && hipMemcpy(d_nz, nzv.data(), nzv.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d_nz);
+    }
+    if ((!corev.empty() &&
+         hipMemcpy(d_core, corev.data(), corev.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        (!leafv.empty() &&
+         hipMemcpy(d_leaf, leafv.data(), leafv.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
+        free_lists();
         return set_error(GBGPU_E_HIP, "vertex list upload failed");
+    }
+    if (!leafv.empty()) {
+        hipLaunchKernelGGL(leaf_nbr_kernel, dim3(grid_for((int64_t)leafv.size())), dim3(kBlock), 0, 0,
+                           g->off, g->nbr, d_leaf, (uint32_t)leafv.size(), d_leafnbr);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            free_lists();
+            return set_error(GBGPU_E_HIP, "leaf neighbour kernel failed");
+        }
     }
     uint4* d_items = nullptr;
     if (hipMalloc(&d_items, std::max<size_t>(items.size(), 1) * sizeof(uint4)) != hipSuccess) {
-        (void)hipFree(d_nz);
+        free_lists();
         return set_error(GBGPU_E_NOMEM, "dense-scan plan allocation failed");
     }
     if (!items.empty() &&
         hipMemcpy(d_items, items.data(), items.size() * sizeof(uint4), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d_items);
+        free_lists();
         return set_error(GBGPU_E_HIP, "dense-scan plan upload failed");
     }
     g->plan = d_items;
     g->nplan = (uint32_t)items.size();
-    g->nz = d_nz;
-    g->nnz = (uint32_t)nzv.size();
+    g->core = d_core;
+    g->ncore = (uint32_t)corev.size();
+    g->leaf = d_leaf;
+    g->leafnbr = d_leafnbr;
+    g->nleaf = (uint32_t)leafv.size();
     return GBGPU_OK;
 }
 
-static int grid_for(int64_t items) {
-    int64_t g = (items + kBlock - 1) / kBlock;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
-}
+
 
 }  // namespace gb
 
@@ -334,14 +372,14 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
     uint32_t* scratch = nullptr;  // [0] flag, [1] max weight
     auto fail = [&](int st) {
         if (g->deg) (void)hipFree(g->deg);
-        if (g->zmask) (void)hipFree(g->zmask);
+        if (g->pruned) (void)hipFree(g->pruned);
         if (g->head) (void)hipFree(g->head);
         if (scratch) (void)hipFree(scratch);
         delete g;
         return st;
     };
     if (hipMalloc(&g->deg, (size_t)n * 4) != hipSuccess ||
-        hipMalloc(&g->zmask, (size_t)g->nwords * 4) != hipSuccess ||
+        hipMalloc(&g->pruned, (size_t)g->nwords * 4) != hipSuccess ||
         hipMalloc(&g->head, (size_t)n * sizeof(uint4)) != hipSuccess ||
         hipMalloc(&scratch, 16) != hipSuccess)
         return fail(set_error(GBGPU_E_NOMEM, "graph metadata allocation failed"));
@@ -381,7 +419,7 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
     g->maxw = weights ? (int32_t)host[1] : 0;
     if (weights && m > 0 && g->maxw < 1) return fail(set_error(GBGPU_E_INVALID, "weight < 1"));
     hipLaunchKernelGGL(degree_kernel, dim3(grid_for(std::max<int64_t>(n, g->nwords))), dim3(kBlock),
-                       0, s, offsets, neighbors, n, g->nwords, g->deg, g->zmask, g->head);
+                       0, s, offsets, neighbors, n, g->nwords, g->deg, g->pruned, g->head);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return fail(set_error(GBGPU_E_HIP, "degree kernel failed"));
     (void)hipFree(scratch);
@@ -400,9 +438,11 @@ int gbgpu_graph_free(gbgpu_graph g) {
         free_wbfs_ws(g->wbfs);
         free_multi_ws(g->multi);
         if (g->plan) (void)hipFree(g->plan);
-        if (g->nz) (void)hipFree(g->nz);
+        if (g->core) (void)hipFree(g->core);
+        if (g->leaf) (void)hipFree(g->leaf);
+        if (g->leafnbr) (void)hipFree(g->leafnbr);
         (void)hipFree(g->deg);
-        (void)hipFree(g->zmask);
+        (void)hipFree(g->pruned);
         (void)hipFree(g->head);
     }
     delete g;

@@ -596,6 +596,7 @@ __global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint3
             a.ctl[2] = 1u;
             if (bprev != kDone) {  // the first launch to find nothing reports it
                 host_store(&a.prog[2], over ? 1u : 0u);
+                __threadfence_system();
                 host_store(&a.prog[1], j + 1);
             }
         } else {

@@ -174,9 +174,10 @@ def test_repeat_runs_identical(gb, rmat16):
 
 @pytest.mark.parametrize("ahead", [1, 3, 8])
 def test_round_log_and_stats(gb, rmat16, ahead):
-    """The round log holds one entry per non-empty frontier of this call (a
-    run with fewer rounds after a longer one must not show stale entries),
-    whatever the launch look-ahead."""
+    """The round log holds one entry per non-empty frontier of this call over
+    the vertices of degree >= 2 (a run with fewer rounds after a longer one
+    must not show stale entries), whatever the launch look-ahead; degree-1
+    vertices are attached after the last round and counted in the stats."""
     g, G = rmat16
     INF = 2**31 - 1
     cyc = gg.cycle(40).with_weights(6, seed=4)
@@ -187,9 +188,12 @@ def test_round_log_and_stats(gb, rmat16, ahead):
         od, _ = oracle.bfs(gg_, s)
         assert st["rounds"] == int(od[od != INF].max()) + 1
         lg = GG.bfs_log()
-        assert len(lg) == st["rounds"]
-        assert int(lg[:, 1].astype(np.int64).sum()) == int((od != INF).sum()) == st["reached"]
-        assert st["launches"] >= st["rounds"] + 1
+        assert st["rounds"] - 1 <= len(lg) <= st["rounds"]
+        assert st["reached"] == int((od != INF).sum())
+        deg = gg_.degrees()
+        core = (od != INF) & ((deg >= 2) | (np.arange(gg_.n) == s))
+        assert int(lg[:, 1].astype(np.int64).sum()) == int(core.sum())
+        assert st["launches"] >= len(lg) + 1
         w, q, sw = gb.wbfs(GG, s, opts={"rounds_per_sync": ahead}, stats=True)
         ow, _ = oracle.wbfs(gg_, s)
         wl = GG.wbfs_log()
