@@ -374,14 +374,50 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         extra["torus256_bfs_gteps"] = round(tg.m / 2 / tt / 1e9, 3)
         extra["torus256_wbfs_ms"] = round(tw * 1e3, 3)
         log(f"torus: BFS {extra['torus256_bfs_ms']} ms, wBFS {extra['torus256_wbfs_ms']} ms")
+        # batched on the high-diameter graph: 64 sources in one call against
+        # the same 64 one at a time (4 timed, scaled)
+        t64 = [int(x) for x in gg.sources(tg, 64, seed=3)]
+        tb = timed(lambda: gb.bfs_multi(T, t64), reps=1)
+        t1 = timed(lambda: [gb.bfs(T, s) for s in t64[:4]], reps=1) * 16
+        extra["torus256_batched64_qps"] = round(64 / tb, 1)
+        extra["torus256_single_qps"] = round(64 / t1, 1)
+        log(f"torus batched 64: {extra['torus256_batched64_qps']} q/s vs one-at-a-time "
+            f"{extra['torus256_single_qps']} q/s")
         del T
     except Exception as ex:  # noqa: BLE001
         extra["error_torus"] = repr(ex)[:300]
+    try:
+        extra.update(run_uneven_batch(gg, gb))
+    except Exception as ex:  # noqa: BLE001
+        extra["error_uneven"] = repr(ex)[:300]
     try:
         extra.update(run_serving(g, G, gg, gb, torch))
     except Exception as ex:  # noqa: BLE001
         extra["error_serving"] = repr(ex)[:300]
     return extra
+
+
+def run_uneven_batch(gg, gb):
+    """256 BFS queries over 8 RMAT graphs of scales 12..20 (edge factor 16),
+    32 per graph, in one gbgpu_bfs_batch call, against the same queries one
+    at a time through gbgpu_bfs."""
+    scales = [12, 13, 14, 15, 16, 17, 18, 20]
+    graphs = [gg.rmat(sc, seed=1) for sc in scales]
+    Gs = [gb.Graph.from_csr(gr, validate=False, with_weights=False) for gr in graphs]
+    qg, qs = [], []
+    for i, gr in enumerate(graphs):
+        for s in gg.sources(gr, 32, seed=3):
+            qg.append(Gs[i])
+            qs.append(int(s))
+    tb = timed(lambda: gb.bfs_batch(qg, qs), reps=2)
+    t1 = timed(lambda: [gb.bfs(Gq, s) for Gq, s in zip(qg, qs)], reps=2)
+    out = {"uneven256_batched_qps": round(len(qs) / tb, 1),
+           "uneven256_single_qps": round(len(qs) / t1, 1)}
+    log(f"uneven batch of 256 over RMAT 12..20: {out['uneven256_batched_qps']} q/s batched vs "
+        f"{out['uneven256_single_qps']} q/s one at a time")
+    for G_ in Gs:
+        G_.free()
+    return out
 
 
 def run_serving(g, G, gg, gb, torch, nq=400):

@@ -155,11 +155,22 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
         __syncthreads();
         if (t < nv) tv[t] = G.VM[v0 + t];
         const int j = t & 63;
-        for (int vi = t >> 6; vi < nv; vi += kBlock / 64) {
-            if (j < k) {
-                tp[vi][j] = G.PS[(size_t)(v0 + vi) * k + j];
-                td[vi][j] = G.DS[(size_t)(v0 + vi) * k + j];
-            }
+        // all of this thread's loads are issued before any LDS store, so each
+        // thread keeps 32 reads in flight
+        constexpr int kRows = 64 / (kBlock / 64);
+        uint32_t lp[kRows], ld[kRows];
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const int vi = (t >> 6) + i * (kBlock / 64);
+            const bool ok = vi < nv && j < k;
+            lp[i] = ok ? G.PS[(size_t)(v0 + vi) * k + j] : 0u;
+            ld[i] = ok ? G.DS[(size_t)(v0 + vi) * k + j] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const int vi = (t >> 6) + i * (kBlock / 64);
+            tp[vi][j] = lp[i];
+            td[vi][j] = ld[i];
         }
         __syncthreads();
         const int q = t & 15;  // four vertices 4q .. 4q+3
