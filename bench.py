@@ -452,6 +452,20 @@ def run_serving(g, G, gg, gb, torch, nq=400):
             sv.poll(t)
         return count / (time.perf_counter() - t0)
     qps_sat = burst(nq // 2)
+
+    # the same kind of mix one query at a time through gbgpu_bfs / gbgpu_wbfs
+    def one_at_a_time(count):
+        r2 = np.random.default_rng(7)
+        t0 = time.perf_counter()
+        for i in range(count):
+            gi = int(r2.integers(0, len(graphs)))
+            kind = int(r2.integers(0, 2))
+            d, p = bufs[gi][i % 16]
+            fn = gb.bfs if kind == 0 else gb.wbfs
+            fn(graphs[gi][1], int(srcsets[gi][i % 32]), dist=d, parent=p)
+        torch.cuda.synchronize()
+        return count / (time.perf_counter() - t0)
+    qps_single = one_at_a_time(nq // 2)
     lam = 0.5 * qps_sat
     lat = []
     pend = []
@@ -472,7 +486,8 @@ def run_serving(g, G, gg, gb, torch, nq=400):
         lat.append((r["t_done_ns"] - r["t_arrive_ns"]) / 1e6)
     sv.close()
     lat = np.array(lat)
-    res = {"serving_saturated_qps": round(qps_sat, 1), "serving_lambda_qps": round(lam, 1),
+    res = {"serving_saturated_qps": round(qps_sat, 1), "serving_single_qps": round(qps_single, 1),
+           "serving_lambda_qps": round(lam, 1),
            "serving_qps": round(nq / el, 1), "serving_p50_ms": round(float(np.percentile(lat, 50)), 3),
            "serving_p99_ms": round(float(np.percentile(lat, 99)), 3),
            "serving_graphs": "rmat24 (w<24), rmat18 (w<18), torus128 (w<21); 50/50 BFS/wBFS"}

@@ -291,13 +291,14 @@ __device__ __forceinline__ void expand_range(const uint32_t* __restrict__ Q,
 
 // Expansion of up to 64 frontier entries held in lanes (vertex u, list start,
 // degree): their edges are concatenated and walked 64 at a time with the same
-// shuffle search as expand_range.  Lanes that are not valid, or have degree
+// shuffle search as expand_range; aux is a per-entry value handed to edge()
+// like the one expand_range takes from the policy.  Lanes that are not valid, or have degree
 // 0, may sit anywhere: their prefix equals the next lane's, and the search
 // returns the largest lane whose prefix is <= the edge index, which always
 // owns edges.  Wave-uniform.
 template <typename Policy>
 __device__ __forceinline__ void expand_lanes(bool valid, uint32_t u, int64_t start, uint32_t deg,
-                                             Policy& pol) {
+                                             Policy& pol, uint32_t aux = 1u) {
     const int l = lane_id();
     const uint32_t d = valid ? deg : 0u;
     const uint32_t inc = wave_incl_sum(d);
@@ -315,7 +316,7 @@ __device__ __forceinline__ void expand_lanes(bool valid, uint32_t u, int64_t sta
         const uint32_t uo = __shfl(u, o, 64);
         const int64_t so = (int64_t)shfl64((uint64_t)start, o);
         const uint32_t po = __shfl(myP, o, 64);
-        pol.edge(act, uo, 1u, so + (int64_t)(t - po), act && t == po);
+        pol.edge(act, uo, __shfl(aux, o, 64), so + (int64_t)(t - po), act && t == po);
         pol.window_done();
     }
 }

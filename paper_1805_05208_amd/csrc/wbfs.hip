@@ -461,13 +461,17 @@ struct PullMinPolicy {
 
     __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
 
-    __device__ __forceinline__ void edge(bool act, uint32_t v, uint32_t, int64_t e, bool) {
+    // room: the largest weight that can still lower v's key (its tentative
+    // distance minus b; equal distances can still lower the parent)
+    __device__ __forceinline__ void edge(bool act, uint32_t v, uint32_t room, int64_t e, bool) {
         if (act) {
-            const uint32_t u = (uint32_t)a->nbr[e];
-            if (test_bit(F, u)) {
-                const unsigned long long c =
-                    ((unsigned long long)(b + (uint32_t)a->wt[e]) << 32) | u;
-                atomicMin(&smin[v - vb], c);
+            const uint32_t w = (uint32_t)a->wt[e];
+            if (w <= room) {
+                const uint32_t u = (uint32_t)a->nbr[e];
+                if (test_bit(F, u)) {
+                    const unsigned long long c = ((unsigned long long)(b + w) << 32) | u;
+                    atomicMin(&smin[v - vb], c);
+                }
             }
         }
     }
@@ -491,14 +495,16 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
         valid = valid && dg > 0u;
         if (!ballot(valid)) return;
         const int64_t st = valid ? a.off[v] : 0;
+        const unsigned long long old = valid ? a.key[v] : 0ull;
+        // unsettled, so its tentative distance is above b
+        const uint32_t room = valid ? (uint32_t)(old >> 32) - b : 0u;
         smin[l] = ~0ull;
         wave_lds_sync();
         PullMinPolicy pol{&a, F, b, smin, it.x};
-        expand_lanes(valid, v, st, dg, pol);
+        expand_lanes(valid, v, st, dg, pol, room);
         wave_lds_sync();
         const unsigned long long best = smin[l];
         if (valid && best != ~0ull) {
-            const unsigned long long old = a.key[v];
             if (best < old) {
                 a.key[v] = best;  // the run owns v: no other writer this step
                 nd = (uint32_t)(best >> 32);
@@ -508,12 +514,14 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
     } else {
         v = it.x;
         if (test_bit(a.S, v)) return;
+        const uint32_t room = (uint32_t)(a.key[v] >> 32) - b;
         unsigned long long best = ~0ull;
         for (uint32_t e = it.z + (uint32_t)l; e < it.w; e += 64) {
+            const uint32_t w = (uint32_t)a.wt[e];
+            if (w > room) continue;
             const uint32_t u = (uint32_t)a.nbr[e];
             if (test_bit(F, u)) {
-                const unsigned long long c =
-                    ((unsigned long long)(b + (uint32_t)a.wt[e]) << 32) | u;
+                const unsigned long long c = ((unsigned long long)(b + w) << 32) | u;
                 best = c < best ? c : best;
             }
         }
