@@ -25,26 +25,26 @@ BFS_SPACE = {
     "pull_light": [4, 8, 16, 32, 64],
     "wave_chunk": [64, 128, 256],
     "grid": [256, 384, 512],
-    "rounds_per_sync": [4, 8, 12, 16, 32],
+    "rounds_per_sync": [1, 2, 3, 4, 6],
     "beta": [-1, 8, 24, 64],
 }
 WBFS_SPACE = {
     "wave_chunk": [64, 128, 256],
     "grid": [128, 256, 384, 512],
-    "rounds_per_sync": [16, 32, 64],
+    "rounds_per_sync": [2, 3, 4, 8],
 }
 MULTI_SPACE = {
     "tau": [5, 10, 20, 40],
     "wave_chunk": [64, 128, 256],
     "grid": [256, 384, 512],
 }
-DEFAULTS = {"tau": 20, "pull_light": 32, "wave_chunk": 256, "grid": 512, "rounds_per_sync": 12,
+DEFAULTS = {"tau": 20, "pull_light": 32, "wave_chunk": 256, "grid": 512, "rounds_per_sync": 3,
             "beta": 24}
 
 
 def coordinate_descent(space: Dict[str, Sequence[int]], start: Dict[str, int],
                        cost: Callable[[Dict[str, int]], Optional[float]], passes: int = 2,
-                       budget_s: float = 60.0) -> Dict:
+                       budget_s: float = 60.0, verbose: bool = False) -> Dict:
     """Minimise cost(opts) one knob at a time.  cost returns None for a
     rejected candidate (e.g. outputs differ).  Pure host logic."""
     t0 = time.time()
@@ -68,6 +68,9 @@ def coordinate_descent(space: Dict[str, Sequence[int]], start: Dict[str, int],
                     continue
                 c = cost(cand)
                 tried[key] = c
+                if verbose:
+                    print(f"  {knob}={val}: " + ("rejected" if c is None else f"{c * 1e3:.3f} ms")
+                          + f" (best {best_cost * 1e3:.3f} ms)", flush=True)
                 if c is None:
                     rejected.append(cand)
                     continue
@@ -97,7 +100,7 @@ def _median_time(fn, reps: int) -> float:
 
 
 def tune_bfs(G, srcs: List[int], reps: int = 3, budget_s: float = 60.0, passes: int = 2,
-             space=None) -> Dict:
+             space=None, verbose: bool = False) -> Dict:
     """Tune gbgpu_bfs on graph G for the given sources."""
     import torch
     import paper_1805_05208_amd as gb
@@ -112,7 +115,7 @@ def tune_bfs(G, srcs: List[int], reps: int = 3, budget_s: float = 60.0, passes: 
                 return None
         return _median_time(lambda: [gb.bfs(G, s, opts=opts) for s in srcs], reps)
 
-    res = coordinate_descent(space or BFS_SPACE, dict(DEFAULTS), cost, passes, budget_s)
+    res = coordinate_descent(space or BFS_SPACE, dict(DEFAULTS), cost, passes, budget_s, verbose)
     res["default_cost"] = cost(dict(DEFAULTS))
     res["signature"] = signature(G.n, G.m, max_degree, st["rounds"])
     res["kind"] = "bfs"
@@ -120,13 +123,13 @@ def tune_bfs(G, srcs: List[int], reps: int = 3, budget_s: float = 60.0, passes: 
 
 
 def tune_wbfs(G, srcs: List[int], reps: int = 2, budget_s: float = 60.0, passes: int = 2,
-              space=None) -> Dict:
+              space=None, verbose: bool = False) -> Dict:
     import torch
     import paper_1805_05208_amd as gb
     ref = [gb.wbfs(G, s) for s in srcs]
     _, _, st = gb.wbfs(G, srcs[0], stats=True)
     max_degree = int((G.offsets[1:] - G.offsets[:-1]).max().item())
-    start = {"wave_chunk": 256, "grid": 512, "rounds_per_sync": 16}
+    start = {"wave_chunk": 256, "grid": 512, "rounds_per_sync": 3}
 
     def cost(opts):
         for s, (d0, p0) in zip(srcs, ref):
@@ -135,7 +138,7 @@ def tune_wbfs(G, srcs: List[int], reps: int = 2, budget_s: float = 60.0, passes:
                 return None
         return _median_time(lambda: [gb.wbfs(G, s, opts=opts) for s in srcs], reps)
 
-    res = coordinate_descent(space or WBFS_SPACE, start, cost, passes, budget_s)
+    res = coordinate_descent(space or WBFS_SPACE, start, cost, passes, budget_s, verbose)
     res["default_cost"] = cost(start)
     res["signature"] = signature(G.n, G.m, max_degree, st["rounds"])
     res["kind"] = "wbfs"
@@ -143,7 +146,7 @@ def tune_wbfs(G, srcs: List[int], reps: int = 2, budget_s: float = 60.0, passes:
 
 
 def tune_multi(G, srcs: List[int], reps: int = 2, budget_s: float = 60.0, passes: int = 1,
-               space=None) -> Dict:
+               space=None, verbose: bool = False) -> Dict:
     import torch
     import paper_1805_05208_amd as gb
     D0, P0 = gb.bfs_multi(G, srcs)
@@ -156,7 +159,7 @@ def tune_multi(G, srcs: List[int], reps: int = 2, budget_s: float = 60.0, passes
             return None
         return _median_time(lambda: gb.bfs_multi(G, srcs, opts=opts), reps)
 
-    res = coordinate_descent(space or MULTI_SPACE, start, cost, passes, budget_s)
+    res = coordinate_descent(space or MULTI_SPACE, start, cost, passes, budget_s, verbose)
     res["default_cost"] = cost(start)
     res["signature"] = signature(G.n, G.m, max_degree, 0)
     res["kind"] = "multi"
@@ -191,7 +194,7 @@ def main():
     import paper_1805_05208_amd as gb
     ap = argparse.ArgumentParser()
     ap.add_argument("--scale", type=int, default=24)
-    ap.add_argument("--sources", type=int, default=4)
+    ap.add_argument("--sources", type=int, default=8)
     ap.add_argument("--budget", type=float, default=120.0)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "tuned.json"))
@@ -204,14 +207,14 @@ def main():
     results = []
     kinds = args.kinds.split(",")
     if "bfs" in kinds:
-        results.append(tune_bfs(G, srcs, budget_s=args.budget))
+        results.append(tune_bfs(G, srcs, budget_s=args.budget, verbose=True))
         print("bfs", results[-1]["opts"], results[-1]["cost"], results[-1]["default_cost"], flush=True)
     if "wbfs" in kinds:
-        results.append(tune_wbfs(G, srcs[:2], budget_s=args.budget))
+        results.append(tune_wbfs(G, srcs[:2], budget_s=args.budget, verbose=True))
         print("wbfs", results[-1]["opts"], results[-1]["cost"], results[-1]["default_cost"], flush=True)
     if "multi" in kinds:
         s64 = [int(s) for s in gg.sources(g, 64, seed=3)]
-        results.append(tune_multi(G, s64, budget_s=args.budget))
+        results.append(tune_multi(G, s64, budget_s=args.budget, verbose=True))
         print("multi", results[-1]["opts"], results[-1]["cost"], results[-1]["default_cost"], flush=True)
     save(results, args.out)
     torch.cuda.synchronize()
