@@ -449,35 +449,7 @@ struct RelaxPolicy {
     __device__ __forceinline__ void window_done() {}
 };
 
-// Dense step, pull side: candidates of the run vertex v from its in-bucket
-// neighbours, folded into the wavefront's per-vertex minimum in LDS.
-struct PullMinPolicy {
-    const WbfsArgs* a;
-    const uint32_t* F;  // bucket bitmap
-    uint32_t b;
-    unsigned long long* smin;
-    uint32_t vb;        // first vertex of the run (slot = v - vb)
-    static constexpr bool kSkipDead = false;
-
-    __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
-
-    // room: the largest weight that can still lower v's key (its tentative
-    // distance minus b; equal distances can still lower the parent)
-    __device__ __forceinline__ void edge(bool act, uint32_t v, uint32_t room, int64_t e, bool) {
-        if (act) {
-            const uint32_t w = (uint32_t)a->wt[e];
-            if (w <= room) {
-                const uint32_t u = (uint32_t)a->nbr[e];
-                if (test_bit(F, u)) {
-                    const unsigned long long c = ((unsigned long long)(b + w) << 32) | u;
-                    atomicMin(&smin[v - vb], c);
-                }
-            }
-        }
-    }
-
-    __device__ __forceinline__ void window_done() {}
-};
+constexpr int kPullWin = 2;  // 64-edge windows whose loads are issued together
 
 // One dense-scan work item: a run of at most 64 consecutive vertices whose
 // lists hold at most 1024 edges together, or a piece of at most 1024 edges of
@@ -500,8 +472,40 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
         const uint32_t room = valid ? (uint32_t)(old >> 32) - b : 0u;
         smin[l] = ~0ull;
         wave_lds_sync();
-        PullMinPolicy pol{&a, F, b, smin, it.x};
-        expand_lanes(valid, v, st, dg, pol, room);
+        // the run's lists, concatenated, walked kPullWin x 64 edges at a time:
+        // every load of those windows is issued before any is used
+        const uint32_t d = valid ? dg : 0u;
+        const uint32_t inc = wave_incl_sum(d);
+        const uint32_t T = __shfl(inc, 63, 64);
+        const uint32_t myP = inc - d;  // lanes without edges share the next lane's prefix
+        for (uint32_t e0 = 0; e0 < T; e0 += kPullWin * kWave) {
+            // (edge indices fit in 32 bits)
+            uint32_t wk[kPullWin], uk[kPullWin], ok[kPullWin], ek[kPullWin];
+#pragma unroll
+            for (int k = 0; k < kPullWin; ++k) {
+                const uint32_t t = e0 + 64u * k + (uint32_t)l;
+                int o = 0;
+#pragma unroll
+                for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+                    const uint32_t pv = __shfl(myP, o + s2, 64);
+                    if (pv <= t) o += s2;
+                }
+                ok[k] = (uint32_t)o;
+                ek[k] = __shfl((uint32_t)st, o, 64) + (t - __shfl(myP, o, 64));
+                wk[k] = t < T ? (uint32_t)a.wt[ek[k]] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kPullWin; ++k) {
+                const uint32_t t = e0 + 64u * k + (uint32_t)l;
+                const uint32_t room_o = __shfl(room, (int)ok[k], 64);
+                uk[k] = (t < T && wk[k] <= room_o) ? (uint32_t)a.nbr[ek[k]] : kNone;
+            }
+#pragma unroll
+            for (int k = 0; k < kPullWin; ++k) {
+                if (uk[k] != kNone && test_bit(F, uk[k]))
+                    atomicMin(&smin[ok[k]], ((unsigned long long)(b + wk[k]) << 32) | uk[k]);
+            }
+        }
         wave_lds_sync();
         const unsigned long long best = smin[l];
         if (valid && best != ~0ull) {
@@ -516,13 +520,24 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
         if (test_bit(a.S, v)) return;
         const uint32_t room = (uint32_t)(a.key[v] >> 32) - b;
         unsigned long long best = ~0ull;
-        for (uint32_t e = it.z + (uint32_t)l; e < it.w; e += 64) {
-            const uint32_t w = (uint32_t)a.wt[e];
-            if (w > room) continue;
-            const uint32_t u = (uint32_t)a.nbr[e];
-            if (test_bit(F, u)) {
-                const unsigned long long c = ((unsigned long long)(b + w) << 32) | u;
-                best = c < best ? c : best;
+        for (uint32_t e0 = it.z; e0 < it.w; e0 += kPullWin * kWave) {
+            uint32_t wk[kPullWin], uk[kPullWin];
+#pragma unroll
+            for (int k = 0; k < kPullWin; ++k) {
+                const uint32_t e = e0 + 64u * k + (uint32_t)l;
+                wk[k] = e < it.w ? (uint32_t)a.wt[e] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kPullWin; ++k) {
+                const uint32_t e = e0 + 64u * k + (uint32_t)l;
+                uk[k] = (e < it.w && wk[k] <= room) ? (uint32_t)a.nbr[e] : kNone;
+            }
+#pragma unroll
+            for (int k = 0; k < kPullWin; ++k) {
+                if (uk[k] != kNone && test_bit(F, uk[k])) {
+                    const unsigned long long c = ((unsigned long long)(b + wk[k]) << 32) | uk[k];
+                    best = c < best ? c : best;
+                }
             }
         }
 #pragma unroll
