@@ -20,17 +20,18 @@ from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 
+GRID_WIDE = [64, 128, 256, 384, 512]
 BFS_SPACE = {
     "tau": [5, 10, 20, 40, 80],
     "pull_light": [4, 8, 16, 32, 64],
     "wave_chunk": [64, 128, 256],
-    "grid": [256, 384, 512],
+    "grid": GRID_WIDE,
     "rounds_per_sync": [1, 2, 3, 4, 6],
     "beta": [-1, 8, 24, 64],
 }
 WBFS_SPACE = {
     "wave_chunk": [64, 128, 256],
-    "grid": [128, 256, 384, 512],
+    "grid": GRID_WIDE,
     "rounds_per_sync": [2, 3, 4, 8],
 }
 MULTI_SPACE = {
@@ -187,12 +188,13 @@ def lookup(path: str, sig: str, kind: str) -> Optional[Dict[str, int]]:
 
 
 def main():
-    """python -m paper_1805_05208_amd.autotune --scale 24 [--budget 120]"""
+    """python -m paper_1805_05208_amd.autotune [--graph rmat|torus] --scale 24 [--budget 120]"""
     import argparse
     import torch
     import graphgen as gg
     import paper_1805_05208_amd as gb
     ap = argparse.ArgumentParser()
+    ap.add_argument("--graph", choices=["rmat", "torus"], default="rmat")
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--sources", type=int, default=8)
     ap.add_argument("--budget", type=float, default=120.0)
@@ -200,7 +202,10 @@ def main():
                                                   "tuned.json"))
     ap.add_argument("--kinds", default="bfs,wbfs,multi")
     args = ap.parse_args()
-    g = gg.rmat(args.scale, seed=1)
+    if args.graph == "torus":
+        g = gg.torus3d(round(2 ** (args.scale / 3)))
+    else:
+        g = gg.rmat(args.scale, seed=1)
     w = gg.weights(g, max(2, int(math.log2(g.n))), seed=2)
     G = gb.Graph(g.offsets, g.nbrs, w, validate=False)
     srcs = [int(s) for s in gg.sources(g, args.sources, seed=3)]
