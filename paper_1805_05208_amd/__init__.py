@@ -131,14 +131,22 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+_OPTS_CACHE: dict = {}
+
+
 def make_opts(opts) -> Optional[Opts]:
     if opts is None:
         return None
     if isinstance(opts, Opts):
         return opts
-    o = Opts()
-    for k, v in dict(opts).items():
-        setattr(o, k, int(v))
+    key = tuple(sorted((k, int(v)) for k, v in dict(opts).items()))
+    o = _OPTS_CACHE.get(key)
+    if o is None:
+        o = Opts()
+        for k, v in key:
+            setattr(o, k, v)
+        if len(_OPTS_CACHE) < 256:
+            _OPTS_CACHE[key] = o
     return o
 
 

@@ -754,6 +754,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     else if (o.profile) GB_HIP(hipEventSynchronize(w->ev1));
     const uint32_t rounds = hp[1] - 1;
     w->last_rounds = rounds;
+    g->depth.store((int32_t)std::max<uint32_t>(rounds, hp[3] + 1u), std::memory_order_relaxed);
     if (st) {
         memset(st, 0, sizeof(*st));
         if (o.profile) {

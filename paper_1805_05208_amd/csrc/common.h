@@ -7,6 +7,7 @@
 #include <stdarg.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <functional>
 #include <mutex>
@@ -68,6 +69,7 @@ struct gbgpu_graph_s {
     int num_cus = 256;
     std::mutex mu;               // serialises calls sharing the workspaces
     std::mutex plan_mu;          // guards the lazily built pull plan
+    std::atomic<int32_t> depth{0};  // BFS depth seen by the last single-source BFS (0: none yet)
     uint4* plan = nullptr;       // owned: dense-scan work items (see ensure_pull_plan)
     uint32_t nplan = 0;
     uint32_t* core = nullptr;    // owned: ids of the vertices of degree >= 2, ascending
@@ -98,6 +100,11 @@ gbgpu_opts resolve_opts(const gbgpu_opts* o);
 int ensure_pull_plan(gbgpu_graph g);
 constexpr uint32_t kPlanCap = 1024;   // max edges of one dense-scan work item
 constexpr uint32_t kPlanHub = 0xFFFFFFFFu;
+// Graphs whose BFS depth exceeds this run batched BFS queries one source at
+// a time: with sources spread over a long diameter most vertices stay in
+// the union of the frontiers for many rounds, so bit-packed batching saves
+// little work and its pushes pay one parent atomicMin per source bit.
+constexpr int32_t kDeepGraph = 64;
 
 // Words of coherent pinned host memory that the traversal kernels write with
 // system-scope stores and the host reads directly (no copy commands): the

@@ -26,6 +26,9 @@ namespace gb {
 
 constexpr int kMaxGroups = 64;
 
+int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
+            gbgpu_stats* st, hipStream_t stream);
+
 struct MsGroupDev {
     const int64_t* off;
     const int32_t* nbr;
@@ -775,6 +778,27 @@ int run_ms_group_mem(const std::vector<MsQuery>& qs, void* mem, void* pin, const
     return ms_run_chunk(qs, groups, 0, 1, mem, pin, o, stream, rounds, &launches);
 }
 
+// Queries answered one source at a time on each graph's own workspace
+// (lock_graphs: take each graph's lock, else the caller holds it).
+int run_singles(const std::vector<MsQuery>& qs, const gbgpu_opts& o, gbgpu_stats* st,
+                       hipStream_t stream, bool lock_graphs) {
+    int launches = 0, rounds = 0;
+    for (const MsQuery& q : qs) {
+        gbgpu_stats s1;
+        std::unique_lock<std::mutex> lk(q.g->mu, std::defer_lock);
+        if (lock_graphs) lk.lock();
+        GB_TRY(run_bfs(q.g, q.src, q.dist, q.parent, o, &s1, stream));
+        launches += s1.launches;
+        rounds = std::max(rounds, s1.rounds);
+    }
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->launches = launches;
+        st->rounds = rounds;
+    }
+    return GBGPU_OK;
+}
+
 }  // namespace gb
 
 using namespace gb;
@@ -794,6 +818,8 @@ int gbgpu_bfs_multi(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist
     for (int i = 0; i < k; ++i)
         qs[i] = MsQuery{g, srcs[i], dist + (size_t)i * g->n, parent + (size_t)i * g->n};
     std::lock_guard<std::mutex> lk(g->mu);
+    if (g->depth.load(std::memory_order_relaxed) > kDeepGraph)
+        return run_singles(qs, opt, st, (hipStream_t)stream, false);
     return run_ms(qs, opt, st, (hipStream_t)stream, &g->multi);
 }
 
@@ -814,8 +840,22 @@ int gbgpu_bfs_batch(const gbgpu_graph* graphs, const int32_t* srcs, int32_t nq,
         qs[i] = MsQuery{graphs[i], srcs[i], dists[i], parents[i]};
     }
     gbgpu_opts opt = resolve_opts(o);
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    return run_ms(qs, opt, st, (hipStream_t)stream, &g_batch_ws);
+    // queries on graphs known to be deep run one at a time, the rest packed
+    std::vector<MsQuery> deep, packed;
+    for (const MsQuery& q : qs)
+        (q.g->depth.load(std::memory_order_relaxed) > kDeepGraph ? deep : packed).push_back(q);
+    gbgpu_stats s1, s2;
+    if (!deep.empty()) GB_TRY(run_singles(deep, opt, st ? &s1 : nullptr, (hipStream_t)stream, true));
+    if (!packed.empty()) {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        GB_TRY(run_ms(packed, opt, st ? &s2 : nullptr, (hipStream_t)stream, &g_batch_ws));
+    }
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->launches = (deep.empty() ? 0 : s1.launches) + (packed.empty() ? 0 : s2.launches);
+        st->rounds = std::max(deep.empty() ? 0 : s1.rounds, packed.empty() ? 0 : s2.rounds);
+    }
+    return GBGPU_OK;
 }
 
 }  // extern "C"

@@ -163,7 +163,10 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
                 gbgpu_graph g = sv->graphs[head.q.graph_id];
                 const int gid = head.q.graph_id;
                 int nsame = 0;
-                if (head.q.kind == GBGPU_QUERY_BFS)
+                // graphs known to be deep answer BFS queries one at a time
+                // (concurrently on the workers) rather than bit-packed
+                if (head.q.kind == GBGPU_QUERY_BFS &&
+                    g->depth.load(std::memory_order_relaxed) <= kDeepGraph)
                     for (auto& p : sv->pending)
                         if (p.q.kind == GBGPU_QUERY_BFS && p.q.graph_id == gid && nsame < 64) ++nsame;
                 // admit the largest batch of same-graph BFS queries that fits

@@ -106,3 +106,25 @@ def test_batch_argument_errors(gb, rmat14):
         gb.bfs_multi(G, [g.n])
     with pytest.raises(gb.GbgpuError):
         gb.bfs_multi(G, [])
+
+
+def test_deep_graphs_batch_one_source_at_a_time(gb):
+    """Once a single-source BFS has shown a graph to be deep, batched calls on
+    it answer each source on its own; mixed batches split between the two
+    paths.  Results equal the oracle either way."""
+    deep, shallow = gg.cycle(300), gg.rmat(10, seed=5)
+    Gd, Gs = gb.Graph.from_csr(deep), gb.Graph.from_csr(shallow)
+    d0, p0, st = gb.bfs(Gd, 0, stats=True)
+    assert st["rounds"] == 151
+    srcs = [0, 17, 150, 299]
+    D, P = gb.bfs_multi(Gd, srcs)
+    check_rows(deep, srcs, D, P, tag="deep multi")
+    ss = [int(x) for x in gg.sources(shallow, 3, seed=2)]
+    graphs = [deep, shallow, deep, shallow, shallow]
+    qg = [Gd, Gs, Gd, Gs, Gs]
+    qs = [3, ss[0], 200, ss[1], ss[2]]
+    dists, parents = gb.bfs_batch(qg, qs)
+    for q, (h, s) in enumerate(zip(graphs, qs)):
+        od, op = oracle.bfs(h, s)
+        assert np.array_equal(dists[q].cpu().numpy(), od), q
+        assert np.array_equal(parents[q].cpu().numpy(), op), q
