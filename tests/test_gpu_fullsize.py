@@ -1,0 +1,101 @@
+"""GPU parity at the benchmark's full sizes, in its launch configuration
+(default options, plus the tuned settings stored for each graph):
+
+* RMAT scale 24: BFS from the first two timed sources and weighted BFS
+  (w < 24) from the first, element by element against the oracle; two rows
+  of a 64-source batch against the oracle;
+* 256^3 torus: BFS against the closed form of distances and min-ID parents,
+  weighted BFS (w < 24) against the definition-level checks.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from checks import check_wbfs
+from test_oracle import torus_closed_form
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TUNED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                     "paper_1805_05208_amd", "tuned.json")
+
+
+@pytest.fixture(scope="module")
+def gb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_05208_amd as m
+    m.lib()
+    return m
+
+
+def tuned(sig_prefix, kind):
+    with open(TUNED) as f:
+        db = json.load(f)
+    for sig, kinds in db.items():
+        if sig.startswith(sig_prefix) and kind in kinds:
+            return kinds[kind]["opts"]
+    return None
+
+
+@pytest.fixture(scope="module")
+def rmat24(gb):
+    g = gg.rmat(24, seed=1)
+    w = gg.weights(g, 24, seed=2)
+    G = gb.Graph(g.offsets, g.nbrs, w, validate=False)
+    yield g, w, G
+    G.free()
+
+
+def assert_same(d, p, od, op, tag):
+    d = np.asarray(d)
+    p = np.asarray(p)
+    bad = np.nonzero((d != od) | (p != op))[0]
+    assert bad.size == 0, (f"{tag}: {bad.size} mismatches, first v={bad[0]}: gpu "
+                           f"({d[bad[0]]},{p[bad[0]]}) oracle ({od[bad[0]]},{op[bad[0]]})")
+
+
+def test_rmat24_bfs(gb, rmat24):
+    g, _, G = rmat24
+    opts = tuned(f"n{g.n}-m{g.m}-", "bfs")
+    for s in [int(x) for x in gg.sources(g, 16, seed=3)[:2]]:
+        d, p = gb.bfs(G, s, opts=opts)
+        od, op = oracle.bfs(g, s)
+        assert_same(d.cpu().numpy(), p.cpu().numpy(), od, op, f"rmat24 bfs src={s}")
+
+
+def test_rmat24_wbfs(gb, rmat24):
+    g, w, G = rmat24
+    s = int(gg.sources(g, 16, seed=3)[0])
+    d, p = gb.wbfs(G, s, opts=tuned(f"n{g.n}-m{g.m}-", "wbfs"))
+    od, op = oracle.wbfs(g, s, weights=w)
+    assert_same(gb.as_u32(d), p.cpu().numpy(), od, op, f"rmat24 wbfs src={s}")
+
+
+def test_rmat24_batched_rows(gb, rmat24):
+    g, _, G = rmat24
+    s64 = [int(x) for x in gg.sources(g, 64, seed=3)]
+    D, P = gb.bfs_multi(G, s64)
+    for i in (5, 40):
+        od, op = oracle.bfs(g, s64[i])
+        assert_same(D[i].cpu().numpy(), P[i].cpu().numpy(), od, op, f"rmat24 batch row {i}")
+    del D, P
+    torch.cuda.empty_cache()
+
+
+def test_torus256(gb):
+    g = gg.torus3d(256).with_weights(24, seed=2)
+    G = gb.Graph.from_csr(g, validate=False)
+    s = int(gg.sources(g, 1, seed=3)[0])
+    prefix = f"n{g.n}-m{g.m}-"
+    d, p = gb.bfs(G, s, opts=tuned(prefix, "bfs"))
+    ed, ep = torus_closed_form(256, s)
+    assert_same(d.cpu().numpy(), p.cpu().numpy(), ed, ep, "torus256 bfs")
+    wd, wp = gb.wbfs(G, s, opts=tuned(prefix, "wbfs"))
+    check_wbfs(g, s, gb.as_u32(wd), wp.cpu().numpy())
+    G.free()
