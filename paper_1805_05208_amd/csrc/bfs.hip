@@ -132,8 +132,7 @@ struct BfsArgs {
     const uint4* head;      // first four neighbours of each vertex
     const uint32_t* nz;     // vertices of degree >= 2 (the ones dense rounds scan)
     uint32_t nnz;
-    const uint32_t* leaf;   // vertices of degree 1 and their one neighbour
-    const uint32_t* leafnbr;
+    const uint2* leaf;      // (vertex of degree 1, its one neighbour)
     uint32_t nleaf;
     uint32_t src;
     uint32_t m32;           // number of stored edges
@@ -149,14 +148,33 @@ struct BfsArgs {
 // ---------------------------------------------------------------------------
 // init: dist = INF, parent = -1, V = zero-degree mask, F = {src}, Q = [src]
 // ---------------------------------------------------------------------------
+// x[0, n) = val except x[sp] = spval, in 16-byte stores from the first
+// 16-byte boundary on (the caller's arrays are only 4-byte aligned).
+__device__ __forceinline__ void fill_u32(uint32_t* x, int64_t n, uint32_t val, int64_t sp,
+                                         uint32_t spval, int64_t tid, int64_t stride) {
+    const int64_t head = min<int64_t>(n, (int64_t)(((16u - ((uintptr_t)x & 15u)) & 15u) >> 2));
+    if (tid < head) x[tid] = tid == sp ? spval : val;
+    const int64_t nv = (n - head) >> 2;
+    uint4* xv = reinterpret_cast<uint4*>(x + head);
+    for (int64_t i = tid; i < nv; i += stride) {
+        const int64_t b = head + 4 * i;
+        uint4 q;
+        q.x = sp == b ? spval : val;
+        q.y = sp == b + 1 ? spval : val;
+        q.z = sp == b + 2 ? spval : val;
+        q.w = sp == b + 3 ? spval : val;
+        xv[i] = q;
+    }
+    const int64_t t0 = head + 4 * nv;
+    if (tid < n - t0) x[t0 + tid] = t0 + tid == sp ? spval : val;
+}
+
 __global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint32_t* pruned,
                                                           uint32_t src) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = tid; v < a.n; v += stride) {
-        a.dist[v] = v == src ? 0 : INT32_MAX;
-        a.parent[v] = v == src ? src : kNone;
-    }
+    fill_u32(reinterpret_cast<uint32_t*>(a.dist), a.n, (uint32_t)INT32_MAX, src, 0u, tid, stride);
+    fill_u32(a.parent, a.n, kNone, src, src, tid, stride);
     for (int64_t w = tid; w < a.nwords; w += stride) {
         a.V[w] = pruned[w];
         a.F0[w] = (w == (int64_t)(src >> 5)) ? (1u << (src & 31)) : 0u;
@@ -485,18 +503,37 @@ __device__ __forceinline__ void pull_bitmap(const BfsArgs& a, uint32_t r, uint32
 // parent of anyone else, so after the last round D[v] = D[u] + 1 and
 // parent[v] = u whenever u was reached.  The last workgroup to finish this
 // pass reports the end of the BFS to the host.
+constexpr int kLeafBatch = 8;
+
 __device__ __forceinline__ void attach_leaves(const BfsArgs& a, uint32_t r, WgQueue& q) {
+    // kLeafBatch records per thread and pass, every load of a pass issued
+    // before its first store: one round trip for the records and one for
+    // the neighbours' distances per pass, instead of two per leaf.  A leaf's
+    // neighbour is never a leaf that this pass writes (it is either of
+    // degree >= 2, finished by the rounds, or a degree-1 source, skipped
+    // here), so reading dist ahead of the stores is safe.
     uint32_t reached = 0, deepest = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.nleaf;
-         i += gridDim.x * blockDim.x) {
-        const uint32_t v = a.leaf[i];
-        const uint32_t u = a.leafnbr[i];
-        const int32_t du = v == a.src ? INT32_MAX : a.dist[u];
-        if (du != INT32_MAX) {
-            a.dist[v] = du + 1;
-            a.parent[v] = u;
-            ++reached;
-            deepest = max(deepest, (uint32_t)du + 1u);
+    const uint32_t nthreads = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x + threadIdx.x; base < a.nleaf;
+         base += kLeafBatch * nthreads) {
+        uint2 rec[kLeafBatch];
+        int32_t du[kLeafBatch];
+#pragma unroll
+        for (int j = 0; j < kLeafBatch; ++j) {
+            const uint32_t i = base + (uint32_t)j * nthreads;
+            rec[j] = i < a.nleaf ? a.leaf[i] : make_uint2(a.src, a.src);
+        }
+#pragma unroll
+        for (int j = 0; j < kLeafBatch; ++j)
+            du[j] = rec[j].x == a.src ? INT32_MAX : a.dist[rec[j].y];
+#pragma unroll
+        for (int j = 0; j < kLeafBatch; ++j) {
+            if (du[j] != INT32_MAX) {
+                a.dist[rec[j].x] = du[j] + 1;
+                a.parent[rec[j].x] = rec[j].y;
+                ++reached;
+                deepest = max(deepest, (uint32_t)du[j] + 1u);
+            }
         }
     }
     reached = wave_sum(reached);
@@ -711,7 +748,6 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.nz = g->core;
     a.nnz = g->ncore;
     a.leaf = g->leaf;
-    a.leafnbr = g->leafnbr;
     a.nleaf = g->nleaf;
     a.src = (uint32_t)src;
     a.m32 = (uint32_t)g->m;
@@ -725,7 +761,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
 
     const int64_t work = std::max<int64_t>(g->nwords / 32, g->m / 4096);
     int grid = (int)std::min<int64_t>(std::max<int64_t>(work, 1), o.grid);
-    int igrid = (int)std::min<int64_t>((g->n + kBlock - 1) / kBlock, 4096);
+    int igrid = (int)std::min<int64_t>((g->n / 4 + kBlock - 1) / kBlock, 4096);
     if (igrid < 1) igrid = 1;
     hipLaunchKernelGGL(bfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, g->pruned,
                        (uint32_t)src);

@@ -74,8 +74,8 @@ struct gbgpu_graph_s {
     uint32_t nplan = 0;
     uint32_t* core = nullptr;    // owned: ids of the vertices of degree >= 2, ascending
     uint32_t ncore = 0;
-    uint32_t* leaf = nullptr;    // owned: ids of the vertices of degree 1, ascending
-    uint32_t* leafnbr = nullptr; // owned: the one neighbour of each of them
+    uint2* leaf = nullptr;       // owned: (vertex, its one neighbour) for every vertex of
+                                 // degree 1, ascending by vertex
     uint32_t nleaf = 0;
     gb::BfsWs* bfs = nullptr;
     gb::WbfsWs* wbfs = nullptr;

@@ -71,6 +71,15 @@ int run_pipeline(volatile uint32_t* prog, hipStream_t stream, int ahead, int64_t
     };
     top_up(ahead);
     GB_HIP(hipGetLastError());
+    // Every launch that finds work writes prog[0] when it starts and the
+    // first one that finds none writes prog[1], so the progress words alone
+    // keep the queue topped up.  The stream itself is queried only after
+    // kQuietMs without a new progress word (a failed device, or launches
+    // exhausted): the runtime answers a query on a busy stream by queueing
+    // a marker, which costs every launch behind it a few microseconds.
+    constexpr double kQuietMs = 2.0;
+    int64_t seen = -1;
+    double quiet_since = 0.0;
     for (uint64_t spin = 1;; ++spin) {
         if (prog[1]) break;
         const int64_t started = prog[0];
@@ -80,18 +89,25 @@ int run_pipeline(volatile uint32_t* prog, hipStream_t stream, int ahead, int64_t
             continue;
         }
         if ((spin & 255u) == 0) {
-            // the queue may have drained before a progress word arrived, or
-            // the device may have failed
-            const hipError_t e = hipStreamQuery(stream);
-            if (e == hipSuccess) {
-                if (prog[1]) break;
-                if (issued >= max_launches)
-                    return set_error(GBGPU_E_HIP, "traversal did not finish within %lld launches",
-                                     (long long)max_launches);
-                top_up(issued + ahead);
-                GB_HIP(hipGetLastError());
-            } else if (e != hipErrorNotReady) {
-                return set_error(GBGPU_E_HIP, "traversal stream failed: %s", hipGetErrorString(e));
+            const double t = now_ms();
+            if (started != seen) {
+                seen = started;
+                quiet_since = t;
+            } else if (t - quiet_since > kQuietMs) {
+                quiet_since = t;
+                const hipError_t e = hipStreamQuery(stream);
+                if (e == hipSuccess) {
+                    if (prog[1]) break;
+                    if (issued >= max_launches)
+                        return set_error(GBGPU_E_HIP,
+                                         "traversal did not finish within %lld launches",
+                                         (long long)max_launches);
+                    top_up(issued + ahead);
+                    GB_HIP(hipGetLastError());
+                } else if (e != hipErrorNotReady) {
+                    return set_error(GBGPU_E_HIP, "traversal stream failed: %s",
+                                     hipGetErrorString(e));
+                }
             }
         }
         if ((spin & 4095u) == 0) std::this_thread::yield(); else cpu_relax();
@@ -227,10 +243,11 @@ static int grid_for(int64_t items) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
 }
 
-__global__ void leaf_nbr_kernel(const int64_t* off, const int32_t* nbr, const uint32_t* leaf,
-                                uint32_t nleaf, uint32_t* leafnbr) {
+// fills in the neighbour half of each (vertex, neighbour) leaf record
+__global__ void leaf_nbr_kernel(const int64_t* off, const int32_t* nbr, uint2* leaf,
+                                uint32_t nleaf) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nleaf; i += gridDim.x * blockDim.x)
-        leafnbr[i] = (uint32_t)nbr[off[leaf[i]]];
+        leaf[i].y = (uint32_t)nbr[off[leaf[i].x]];
 }
 
 // Dense-scan plan: work items that cover every non-isolated vertex once.
@@ -272,35 +289,35 @@ int ensure_pull_plan(gbgpu_graph g) {
     }
     // vertex lists for the BFS: degree >= 2 (scanned by dense rounds) and
     // degree 1 (attached after the rounds through their one neighbour)
-    std::vector<uint32_t> corev, leafv;
+    std::vector<uint32_t> corev;
+    std::vector<uint2> leafv;
     corev.reserve((size_t)n);
     for (int64_t v = 0; v < n; ++v) {
         const int64_t d = off[v + 1] - off[v];
         if (d >= 2) corev.push_back((uint32_t)v);
-        else if (d == 1) leafv.push_back((uint32_t)v);
+        else if (d == 1) leafv.push_back(make_uint2((uint32_t)v, 0u));
     }
-    uint32_t *d_core = nullptr, *d_leaf = nullptr, *d_leafnbr = nullptr;
+    uint32_t* d_core = nullptr;
+    uint2* d_leaf = nullptr;
     auto free_lists = [&]() {
         if (d_core) (void)hipFree(d_core);
         if (d_leaf) (void)hipFree(d_leaf);
-        if (d_leafnbr) (void)hipFree(d_leafnbr);
     };
     if (hipMalloc(&d_core, std::max<size_t>(corev.size(), 1) * 4) != hipSuccess ||
-        hipMalloc(&d_leaf, std::max<size_t>(leafv.size(), 1) * 4) != hipSuccess ||
-        hipMalloc(&d_leafnbr, std::max<size_t>(leafv.size(), 1) * 4) != hipSuccess) {
+        hipMalloc(&d_leaf, std::max<size_t>(leafv.size(), 1) * sizeof(uint2)) != hipSuccess) {
         free_lists();
         return set_error(GBGPU_E_NOMEM, "vertex list allocation failed");
     }
     if ((!corev.empty() &&
          hipMemcpy(d_core, corev.data(), corev.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
-        (!leafv.empty() &&
-         hipMemcpy(d_leaf, leafv.data(), leafv.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
+        (!leafv.empty() && hipMemcpy(d_leaf, leafv.data(), leafv.size() * sizeof(uint2),
+                                     hipMemcpyHostToDevice) != hipSuccess)) {
         free_lists();
         return set_error(GBGPU_E_HIP, "vertex list upload failed");
     }
     if (!leafv.empty()) {
         hipLaunchKernelGGL(leaf_nbr_kernel, dim3(grid_for((int64_t)leafv.size())), dim3(kBlock), 0, 0,
-                           g->off, g->nbr, d_leaf, (uint32_t)leafv.size(), d_leafnbr);
+                           g->off, g->nbr, d_leaf, (uint32_t)leafv.size());
         if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
             free_lists();
             return set_error(GBGPU_E_HIP, "leaf neighbour kernel failed");
@@ -322,7 +339,6 @@ int ensure_pull_plan(gbgpu_graph g) {
     g->core = d_core;
     g->ncore = (uint32_t)corev.size();
     g->leaf = d_leaf;
-    g->leafnbr = d_leafnbr;
     g->nleaf = (uint32_t)leafv.size();
     return GBGPU_OK;
 }
@@ -440,7 +456,6 @@ int gbgpu_graph_free(gbgpu_graph g) {
         if (g->plan) (void)hipFree(g->plan);
         if (g->core) (void)hipFree(g->core);
         if (g->leaf) (void)hipFree(g->leaf);
-        if (g->leafnbr) (void)hipFree(g->leafnbr);
         (void)hipFree(g->deg);
         (void)hipFree(g->pruned);
         (void)hipFree(g->head);
