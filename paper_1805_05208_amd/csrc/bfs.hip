@@ -131,6 +131,7 @@ struct BfsArgs {
     uint32_t* log;          // host round log (device address)
     const uint4* head;      // first four neighbours of each vertex
     const uint32_t* nz;     // vertices of degree >= 2 (the ones dense rounds scan)
+    const uint4* nz_head;   // their head records, in the same order
     uint32_t nnz;
     const uint2* leaf;      // (vertex of degree 1, its one neighbour)
     uint32_t nleaf;
@@ -269,7 +270,8 @@ typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 // to be unvisited.
 template <bool kCheck>
 __device__ __forceinline__ void pull_vertices(const BfsArgs& a, uint32_t r,
-                                              const uint32_t (&v)[kPullG], const bool (&in)[kPullG],
+                                              const uint32_t (&v)[kPullG], const uint32_t (&hi)[kPullG],
+                                              const bool (&in)[kPullG],
                                               const uint32_t* __restrict__ Fc, uint32_t* Fn,
                                               uint32_t& found, uint32_t& dsum) {
     const int l = lane_id();
@@ -282,12 +284,16 @@ __device__ __forceinline__ void pull_vertices(const BfsArgs& a, uint32_t r,
     bool any_unvis = false;
 #pragma unroll
     for (int j = 0; j < kPullG; ++j) {
+        // list candidates read their head record by list position, so the
+        // load needs neither the vertex id nor the visited test first
         uint32_t vw = 0u;
+        uint4 hh = make_uint4(kNone, kNone, kNone, kNone);
+        if (in[j]) hh = kCheck ? a.nz_head[hi[j]] : a.head[hi[j]];
         if constexpr (kCheck) {
             if (in[j]) vw = a.V[v[j] >> 5] | Fc[v[j] >> 5];
         }
         unvis[j] = in[j] && !((vw >> (v[j] & 31)) & 1u);
-        h4[j] = unvis[j] ? a.head[v[j]] : make_uint4(kNone, kNone, kNone, kNone);
+        h4[j] = unvis[j] ? hh : make_uint4(kNone, kNone, kNone, kNone);
         hit[j] = kNone;
         any_unvis |= unvis[j];
     }
@@ -436,15 +442,16 @@ __device__ __forceinline__ void pull_list(const BfsArgs& a, uint32_t r, uint32_t
     const int l = lane_id();
     const uint32_t per = 64u * kPullG;
     for (uint32_t base = gwave * per; base < a.nnz; base += nwaves * per) {
-        uint32_t v[kPullG];
+        uint32_t v[kPullG], hi[kPullG];
         bool in[kPullG];
 #pragma unroll
         for (int j = 0; j < kPullG; ++j) {
             const uint32_t i = base + (uint32_t)l + 64u * j;
             in[j] = i < a.nnz;
             v[j] = in[j] ? a.nz[i] : 0u;
+            hi[j] = i;
         }
-        pull_vertices<true>(a, r, v, in, Fc, Fn, found, dsum);
+        pull_vertices<true>(a, r, v, hi, in, Fc, Fn, found, dsum);
     }
 }
 
@@ -493,7 +500,7 @@ __device__ __forceinline__ void pull_bitmap(const BfsArgs& a, uint32_t r, uint32
                 const uint32_t k = idx - __shfl(excl, o, 64);
                 v[j] = in[j] ? (uint32_t)((blk * 64 + o) * 32) + select_bit(xo, k) : 0u;
             }
-            pull_vertices<false>(a, r, v, in, Fc, Fn, found, dsum);
+            pull_vertices<false>(a, r, v, v, in, Fc, Fn, found, dsum);
         }
     }
 }
@@ -746,6 +753,7 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.log = w->hl.d + kHostLogOff;
     a.head = g->head;
     a.nz = g->core;
+    a.nz_head = g->core_head;
     a.nnz = g->ncore;
     a.leaf = g->leaf;
     a.nleaf = g->nleaf;

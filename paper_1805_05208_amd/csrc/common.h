@@ -73,6 +73,7 @@ struct gbgpu_graph_s {
     uint4* plan = nullptr;       // owned: dense-scan work items (see ensure_pull_plan)
     uint32_t nplan = 0;
     uint32_t* core = nullptr;    // owned: ids of the vertices of degree >= 2, ascending
+    uint4* core_head = nullptr;  // owned: their head records, in the same order
     uint32_t ncore = 0;
     uint2* leaf = nullptr;       // owned: (vertex, its one neighbour) for every vertex of
                                  // degree 1, ascending by vertex

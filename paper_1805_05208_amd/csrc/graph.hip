@@ -243,6 +243,12 @@ static int grid_for(int64_t items) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
 }
 
+__global__ void gather_head_kernel(const uint4* head, const uint32_t* core, uint32_t ncore,
+                                   uint4* core_head) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ncore; i += gridDim.x * blockDim.x)
+        core_head[i] = head[core[i]];
+}
+
 // fills in the neighbour half of each (vertex, neighbour) leaf record
 __global__ void leaf_nbr_kernel(const int64_t* off, const int32_t* nbr, uint2* leaf,
                                 uint32_t nleaf) {
@@ -298,12 +304,15 @@ int ensure_pull_plan(gbgpu_graph g) {
         else if (d == 1) leafv.push_back(make_uint2((uint32_t)v, 0u));
     }
     uint32_t* d_core = nullptr;
+    uint4* d_core_head = nullptr;
     uint2* d_leaf = nullptr;
     auto free_lists = [&]() {
         if (d_core) (void)hipFree(d_core);
+        if (d_core_head) (void)hipFree(d_core_head);
         if (d_leaf) (void)hipFree(d_leaf);
     };
     if (hipMalloc(&d_core, std::max<size_t>(corev.size(), 1) * 4) != hipSuccess ||
+        hipMalloc(&d_core_head, std::max<size_t>(corev.size(), 1) * sizeof(uint4)) != hipSuccess ||
         hipMalloc(&d_leaf, std::max<size_t>(leafv.size(), 1) * sizeof(uint2)) != hipSuccess) {
         free_lists();
         return set_error(GBGPU_E_NOMEM, "vertex list allocation failed");
@@ -314,6 +323,14 @@ int ensure_pull_plan(gbgpu_graph g) {
                                      hipMemcpyHostToDevice) != hipSuccess)) {
         free_lists();
         return set_error(GBGPU_E_HIP, "vertex list upload failed");
+    }
+    if (!corev.empty()) {
+        hipLaunchKernelGGL(gather_head_kernel, dim3(grid_for((int64_t)corev.size())), dim3(kBlock),
+                           0, 0, g->head, d_core, (uint32_t)corev.size(), d_core_head);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            free_lists();
+            return set_error(GBGPU_E_HIP, "head record gather failed");
+        }
     }
     if (!leafv.empty()) {
         hipLaunchKernelGGL(leaf_nbr_kernel, dim3(grid_for((int64_t)leafv.size())), dim3(kBlock), 0, 0,
@@ -337,6 +354,7 @@ int ensure_pull_plan(gbgpu_graph g) {
     g->plan = d_items;
     g->nplan = (uint32_t)items.size();
     g->core = d_core;
+    g->core_head = d_core_head;
     g->ncore = (uint32_t)corev.size();
     g->leaf = d_leaf;
     g->nleaf = (uint32_t)leafv.size();
@@ -455,6 +473,7 @@ int gbgpu_graph_free(gbgpu_graph g) {
         free_multi_ws(g->multi);
         if (g->plan) (void)hipFree(g->plan);
         if (g->core) (void)hipFree(g->core);
+        if (g->core_head) (void)hipFree(g->core_head);
         if (g->leaf) (void)hipFree(g->leaf);
         (void)hipFree(g->deg);
         (void)hipFree(g->pruned);
