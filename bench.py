@@ -47,9 +47,14 @@ def measured_traffic(name):
     return None
 
 
+# the sources that decide what bfs_round_kernel reads and writes: the kernel,
+# its shared device helpers, and the load-time structures it scans
+ROUND_KERNEL_SOURCES = ("bfs.hip", "common.h", "emit.h", "graph.hip")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1805_05208_amd", "csrc"))):
+    for f in ROUND_KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1805_05208_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
