@@ -25,6 +25,8 @@
 namespace gb {
 
 constexpr int kMaxGroups = 64;
+// 64-edge windows a wavefront of the dense scan loads before it updates
+constexpr int kMsWin = 2;
 
 int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
             gbgpu_stats* st, hipStream_t stream);
@@ -324,21 +326,21 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
             e = max(e, __shfl(s, first_lane(after), 64));
             continue;
         }
-        // four windows: owners, then all loads, then the ordered updates
-        int ow[4];
-        uint32_t u[4];
-        unsigned long long fu[4];
+        // kMsWin windows: owners, then all loads, then the ordered updates
+        int ow[kMsWin];
+        uint32_t u[kMsWin];
+        unsigned long long fu[kMsWin];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kMsWin; ++k) {
             const uint32_t t = e + 64u * k + (uint32_t)l;
             ow[k] = owner(t);
             const bool act = t < T && ((live >> ow[k]) & 1ull);
             u[k] = act ? (uint32_t)G.nbr[base + t] : kNone;
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) fu[k] = u[k] != kNone ? Fc[u[k]] : 0ull;
+        for (int k = 0; k < kMsWin; ++k) fu[k] = u[k] != kNone ? Fc[u[k]] : 0ull;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kMsWin; ++k) {
             const uint32_t eb = e + 64u * k;
             if (eb >= T) break;
             const int o = ow[k];
@@ -377,7 +379,7 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
             if (hasw) acc |= tot;
         }
         live = ballot(need != 0ull && acc != need);
-        e += 256u;
+        e += 64u * kMsWin;
     }
     const bool got = acc != 0ull;
     if (in && got) {
@@ -435,7 +437,11 @@ __device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, u
     if (m && emit) wave_direct_emit(claim && l == 0, v, (uint32_t)(oe - ob), m, out);
 }
 
-__global__ __launch_bounds__(kRBlock, 8) void ms_round_kernel(MsArgs A, uint32_t r) {
+// One workgroup per CU at most (up to 128 VGPRs): the dense scan's state
+// for a window of edges then stays in registers; at the 64-VGPR limit of
+// two workgroups per CU it spilled to scratch, and the spill traffic cost
+// more than the lost occupancy.
+__global__ __launch_bounds__(kRBlock, 1) void ms_round_kernel(MsArgs A, uint32_t r) {
     __shared__ uint32_t s_units[kMaxGroups + 1];
     __shared__ uint32_t s_push[kMaxGroups];
     __shared__ uint32_t s_wc[kMaxGroups];
