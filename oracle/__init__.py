@@ -15,6 +15,11 @@ Path Problems"), with parents fixed by the minimum-ID rule:
 * :func:`wbfs` -- integral-weight distances (uint32, 0xFFFFFFFF =
   unreachable), computed with Dial's bucketed Dijkstra, and
   parent[v] = min{u in N(v): D[u] + w(u,v) == D[v]}.
+* :func:`bellman_ford` -- general-weight SSSP distances (int64, INT64_MAX =
+  unreachable, INT64_MIN = minus infinity behind a reachable negative
+  cycle), textbook Bellman-Ford.
+* :func:`widest_path` -- widest (bottleneck) path widths (uint32, source =
+  0xFFFFFFFF, unreachable = 0), Dijkstra on a max-heap of widths.
 """
 from __future__ import annotations
 
@@ -31,6 +36,9 @@ _lib = None
 
 BFS_INF = np.int32(2**31 - 1)
 WBFS_INF = np.uint32(0xFFFFFFFF)
+SSSP_INF = np.int64(2**63 - 1)
+SSSP_NEG_INF = np.int64(-2**63)
+WIDE_SRC = np.uint32(0xFFFFFFFF)
 
 
 def build(force: bool = True) -> str:
@@ -53,6 +61,10 @@ def _load():
         lib.oracle_bfs.restype = ctypes.c_int
         lib.oracle_wbfs.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P]
         lib.oracle_wbfs.restype = ctypes.c_int
+        lib.oracle_bellman_ford.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P]
+        lib.oracle_bellman_ford.restype = ctypes.c_int
+        lib.oracle_widest_path.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P]
+        lib.oracle_widest_path.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -95,3 +107,35 @@ def wbfs(g, src: int, weights=None):
     if rc != 0:
         raise ValueError(f"oracle_wbfs failed with code {rc}")
     return dist, parent
+
+
+def _weights_of(g, weights):
+    w = g.weights if weights is None else weights
+    if w is None:
+        raise ValueError("weighted graph required")
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    if ww.size == 0:
+        ww = np.ones(1, dtype=np.int32)
+    return ww
+
+
+def bellman_ford(g, src: int, weights=None):
+    """Return dist int64[n] for general-weight SSSP (any int32 weights)."""
+    off, nb = _csr_arrays(g)
+    ww = _weights_of(g, weights)
+    dist = np.empty(g.n, dtype=np.int64)
+    rc = _load().oracle_bellman_ford(g.n, _p(off), _p(nb), _p(ww), int(src), _p(dist))
+    if rc != 0:
+        raise ValueError(f"oracle_bellman_ford failed with code {rc}")
+    return dist
+
+
+def widest_path(g, src: int, weights=None):
+    """Return width uint32[n] for the widest (bottleneck) path problem."""
+    off, nb = _csr_arrays(g)
+    ww = _weights_of(g, weights)
+    width = np.empty(g.n, dtype=np.uint32)
+    rc = _load().oracle_widest_path(g.n, _p(off), _p(nb), _p(ww), int(src), _p(width))
+    if rc != 0:
+        raise ValueError(f"oracle_widest_path failed with code {rc}")
+    return width

@@ -23,6 +23,22 @@
  * with parent[src] = src and parent = -1 for unreachable vertices.
  *
  * Encodings of infinity: BFS int32 INT32_MAX, wBFS uint32 0xFFFFFFFF.
+ *
+ * Two more problems of the same section are computed from their definitions
+ * (distances / widths only; the statements ask for no parents):
+ *   General-weight SSSP: D[v] = shortest-path distance from src over int32
+ *         weights of any sign (int64), INT64_MAX when unreachable, INT64_MIN
+ *         (minus infinity) when a negative cycle reachable from src reaches
+ *         v.  Textbook Bellman-Ford: passes over every edge until none
+ *         lowers a distance (at most n - 1), one more pass to find the
+ *         vertices a negative cycle still lowers, then every vertex reachable
+ *         from those gets minus infinity.
+ *   Widest path: W[v] = maximum over src-v paths of the smallest weight on
+ *         the path (weights >= 1, uint32).  The source's width is that of the
+ *         empty path, 0xFFFFFFFF; an unreachable vertex gets 0, the maximum
+ *         over no paths (the statement's "infinity when unreachable" would
+ *         collide with the source's own width).  Textbook method: Dijkstra's
+ *         algorithm on a max-heap of widths.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -164,5 +180,183 @@ int oracle_wbfs(int64_t n, const int64_t* offsets, const int32_t* nbrs,
     }
     parent[src] = src;
     free(d);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* General-weight SSSP (Bellman-Ford).                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
+ * The CSR may be directed here (edge e goes from its list's owner to
+ * nbrs[e]); distances of simple paths fit in int64 for any int32 weights. */
+int oracle_bellman_ford(int64_t n, const int64_t* offsets, const int32_t* nbrs,
+                        const int32_t* w, int32_t src, int64_t* dist) {
+    if (n <= 0 || src < 0 || src >= n) return -1;
+    /* With a negative cycle, in-place passes can follow walks of up to n
+     * edges per pass, n^2 * 2^31 in all: negative weights are accepted on
+     * graphs small enough for that to fit in int64. */
+    if (n > 65536) {
+        for (int64_t e = 0; e < offsets[n]; ++e)
+            if (w[e] < 0) return -1;
+    }
+    const int64_t INF = INT64_MAX;
+    for (int64_t v = 0; v < n; ++v) dist[v] = INF;
+    dist[src] = 0;
+    /* passes over all edges until a pass changes nothing; a graph without a
+     * reachable negative cycle settles within n - 1 passes */
+    int changed = 1;
+    for (int64_t pass = 0; pass < n - 1 && changed; ++pass) {
+        changed = 0;
+        for (int64_t u = 0; u < n; ++u) {
+            if (dist[u] == INF) continue;
+            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+                const int64_t nd = dist[u] + (int64_t)w[e];
+                if (nd < dist[nbrs[e]]) {
+                    dist[nbrs[e]] = nd;
+                    changed = 1;
+                }
+            }
+        }
+    }
+    if (!changed) return 0;
+    /* one more pass: every vertex that can still be lowered lies on or
+     * behind a negative cycle reachable from src */
+    unsigned char* neg = (unsigned char*)calloc((size_t)n, 1);
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!neg || !queue) {
+        free(neg);
+        free(queue);
+        return -2;
+    }
+    int64_t tail = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        if (dist[u] == INF) continue;
+        for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+            const int32_t v = nbrs[e];
+            if (dist[u] + (int64_t)w[e] < dist[v] && !neg[v]) {
+                neg[v] = 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    /* minus infinity spreads to everything reachable from those vertices */
+    for (int64_t head = 0; head < tail; ++head) {
+        const int32_t u = queue[head];
+        for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+            const int32_t v = nbrs[e];
+            if (!neg[v]) {
+                neg[v] = 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    for (int64_t v = 0; v < n; ++v)
+        if (neg[v]) dist[v] = INT64_MIN;
+    free(neg);
+    free(queue);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Widest (bottleneck) path.                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Binary max-heap of vertices keyed by their current width, with the
+ * position of every vertex so that a width can be raised in place. */
+typedef struct {
+    int32_t* v;     /* heap slots */
+    int64_t* pos;   /* slot of each vertex, -1 when not in the heap */
+    const uint32_t* key;
+    int64_t len;
+} maxheap;
+
+static void mh_swap(maxheap* h, int64_t i, int64_t j) {
+    int32_t t = h->v[i];
+    h->v[i] = h->v[j];
+    h->v[j] = t;
+    h->pos[h->v[i]] = i;
+    h->pos[h->v[j]] = j;
+}
+
+static void mh_up(maxheap* h, int64_t i) {
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h->key[h->v[p]] >= h->key[h->v[i]]) break;
+        mh_swap(h, i, p);
+        i = p;
+    }
+}
+
+static void mh_down(maxheap* h, int64_t i) {
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, b = i;
+        if (l < h->len && h->key[h->v[l]] > h->key[h->v[b]]) b = l;
+        if (r < h->len && h->key[h->v[r]] > h->key[h->v[b]]) b = r;
+        if (b == i) break;
+        mh_swap(h, i, b);
+        i = b;
+    }
+}
+
+/* Returns 0 on success, -1 on bad arguments (weights < 1), -2 on
+ * allocation failure. */
+int oracle_widest_path(int64_t n, const int64_t* offsets, const int32_t* nbrs,
+                       const int32_t* w, int32_t src, uint32_t* width) {
+    if (n <= 0 || src < 0 || src >= n) return -1;
+    const int64_t m = offsets[n];
+    for (int64_t e = 0; e < m; ++e)
+        if (w[e] < 1) return -1;
+    maxheap h;
+    h.v = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    h.pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    unsigned char* done = (unsigned char*)calloc((size_t)n, 1);
+    if (!h.v || !h.pos || !done) {
+        free(h.v);
+        free(h.pos);
+        free(done);
+        return -2;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        width[v] = 0;
+        h.pos[v] = -1;
+    }
+    h.key = width;
+    h.len = 0;
+    width[src] = 0xFFFFFFFFu;
+    h.v[0] = src;
+    h.pos[src] = 0;
+    h.len = 1;
+    /* Dijkstra with the roles of min and + taken by max and min: the widest
+     * unsettled vertex cannot be widened any more, since every path through
+     * another unsettled vertex is at most that vertex's width. */
+    while (h.len > 0) {
+        const int32_t u = h.v[0];
+        h.len--;
+        if (h.len > 0) {
+            h.v[0] = h.v[h.len];
+            h.pos[h.v[0]] = 0;
+            mh_down(&h, 0);
+        }
+        h.pos[u] = -1;
+        done[u] = 1;
+        for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+            const int32_t v = nbrs[e];
+            if (done[v]) continue;
+            const uint32_t c = width[u] < (uint32_t)w[e] ? width[u] : (uint32_t)w[e];
+            if (c > width[v]) {
+                width[v] = c;
+                if (h.pos[v] < 0) {
+                    h.v[h.len] = v;
+                    h.pos[v] = h.len;
+                    h.len++;
+                }
+                mh_up(&h, h.pos[v]);
+            }
+        }
+    }
+    free(h.v);
+    free(h.pos);
+    free(done);
     return 0;
 }
