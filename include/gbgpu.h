@@ -68,7 +68,10 @@ typedef struct gbgpu_graph_s* gbgpu_graph;
 /* Load flags. */
 enum {
     GBGPU_SYMMETRIC = 1u, /* caller asserts every edge is stored both ways   */
-    GBGPU_VALIDATE = 2u   /* check the CSR on the device (see gbgpu_load_csr) */
+    GBGPU_VALIDATE = 2u,  /* check the CSR on the device (see gbgpu_load_csr) */
+    GBGPU_SIGNED_WEIGHTS = 4u /* weights may be any int32 (zero and negative
+                                 ones allowed; only gbgpu_bellman_ford then
+                                 accepts the graph's weights)               */
 };
 
 /* Tuning knobs; a zero field selects the built-in (or autotuned) default.
@@ -117,8 +120,10 @@ typedef struct {
  *   offsets    dev int64[n+1], offsets[0] = 0, offsets[n] = m, non-decreasing
  *   neighbors  dev int32[m], each list sorted strictly ascending (no
  *              duplicates), no self loops, ids in [0, n)
- *   weights    dev int32[m] aligned with neighbors, all >= 1, w(u,v) = w(v,u);
- *              NULL for an unweighted graph (BFS only)
+ *   weights    dev int32[m] aligned with neighbors, w(u,v) = w(v,u), all >= 1
+ *              unless GBGPU_SIGNED_WEIGHTS is given; NULL for an unweighted
+ *              graph (BFS only).  The smallest weight is checked with or
+ *              without GBGPU_VALIDATE.
  *   flags      must include GBGPU_SYMMETRIC (the dense pull reads a vertex's
  *              own list as its in-edges); GBGPU_VALIDATE checks every property
  *              above, including symmetry of edges and weights, on the device
@@ -127,8 +132,9 @@ typedef struct {
  * Ownership: the graph arrays are borrowed -- the caller keeps them alive and
  * unchanged until gbgpu_graph_free.  The handle owns a degree array, a
  * zero-degree bitmap and lazily sized traversal workspaces.
- * Errors: E_INVALID for null pointers, bad sizes, a missing SYMMETRIC flag or
- * a failed validation; E_UNSUPPORTED for n or m beyond the limits above. */
+ * Errors: E_INVALID for null pointers, bad sizes, a missing SYMMETRIC flag,
+ * a weight below 1 without GBGPU_SIGNED_WEIGHTS, or a failed validation;
+ * E_UNSUPPORTED for n or m beyond the limits above. */
 int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets,
                    const int32_t* neighbors, const int32_t* weights,
                    uint32_t flags, void* stream, gbgpu_graph* out);
@@ -155,12 +161,46 @@ int gbgpu_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
  * with priority-write).
  *   dist    dev uint32[n] output, 0xFFFFFFFF for unreachable
  *   parent  dev int32[n] output, min-ID tight parent, -1 for unreachable
- * Errors: E_INVALID (no weights, bad src, null output), E_OVERFLOW when
- * max_weight * n >= 0xFFFFFFFE (a tentative distance could overflow),
- * E_UNSUPPORTED when max_weight > 2047, E_NOMEM when the bucket workspace
- * cannot be allocated. */
+ * Errors: E_INVALID (no weights, a weight below 1, bad src, null output),
+ * E_OVERFLOW when max_weight * n >= 0xFFFFFFFE (a tentative distance could
+ * overflow), E_UNSUPPORTED when max_weight > 2047, E_NOMEM when the bucket
+ * workspace cannot be allocated. */
 int gbgpu_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent,
                const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
+/* Single-source general-weight SSSP (General-Weight SSSP problem statement;
+ * the paper's frontier-based Bellman-Ford algorithm box: every round relaxes
+ * the out-edges of the vertices whose distance dropped in the round before,
+ * with a priority-write (atomic minimum), until no distance drops; the
+ * sparse/dense switch of edgeMap applies).
+ *   src     source vertex in [0, n)
+ *   dist    dev int64[n] output: shortest-path distance; INT64_MAX for
+ *           unreachable; INT64_MIN (minus infinity) for every vertex a
+ *           negative cycle reachable from src reaches.  Weights are int32 of
+ *           any sign (load with GBGPU_SIGNED_WEIGHTS for zero or negative
+ *           ones).  The graph is symmetric, so a negative edge reachable from
+ *           src is a negative cycle (u, v, u): then the whole component of
+ *           src is minus infinity, which a reachability pass detects before
+ *           any relaxation; otherwise the component's weights are >= 0 and
+ *           the rounds end.
+ *   o, st   optional (NULL allowed); st->rounds = relaxation rounds
+ * Errors: E_INVALID for a null handle/output, no weights or src out of
+ * range.  The call returns when dist is complete. */
+int gbgpu_bellman_ford(gbgpu_graph g, int32_t src, int64_t* dist, const gbgpu_opts* o,
+                       gbgpu_stats* st, void* stream);
+
+/* Single-source widest (bottleneck) path (Widest Path problem statement; the
+ * paper runs it as Bellman-Ford over the (max, min) semiring: the same
+ * rounds, with min(width(u), w(u,v)) in place of D(u) + w(u,v) and an atomic
+ * maximum in place of the minimum).
+ *   width   dev uint32[n] output: the largest, over src-v paths, smallest
+ *           weight on the path; 0xFFFFFFFF for src (the empty path); 0 for
+ *           unreachable vertices (the maximum over no paths -- every real
+ *           width is >= 1)
+ * Errors: E_INVALID for a null handle/output, no weights, a weight below 1
+ * or src out of range.  The call returns when width is complete. */
+int gbgpu_widest_path(gbgpu_graph g, int32_t src, uint32_t* width, const gbgpu_opts* o,
+                      gbgpu_stats* st, void* stream);
 
 /* Batched multi-source BFS on one graph: k independent BFS problems solved
  * together with one 64-bit frontier mask per vertex and group of 64 sources.

@@ -19,14 +19,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgbgpu.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_OVERFLOW, E_AGAIN, E_NOTFOUND = range(8)
-SYMMETRIC, VALIDATE = 1, 2
+SYMMETRIC, VALIDATE, SIGNED_WEIGHTS = 1, 2, 4
 QUERY_BFS, QUERY_WBFS = 0, 1
 BFS_INF = 2**31 - 1
 WBFS_INF = 0xFFFFFFFF
 
 EXPORTED = [
     "gbgpu_last_error", "gbgpu_version", "gbgpu_load_csr", "gbgpu_graph_free",
-    "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bfs_multi", "gbgpu_bfs_batch",
+    "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bellman_ford", "gbgpu_widest_path",
+    "gbgpu_bfs_multi", "gbgpu_bfs_batch",
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
     "gbgpu_debug_bfs_log", "gbgpu_debug_wbfs_log", "gbgpu_debug_arena_selftest",
@@ -98,6 +99,8 @@ def lib() -> ctypes.CDLL:
             "gbgpu_graph_info": ([P, P, P, P], ctypes.c_int),
             "gbgpu_bfs": ([P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_wbfs": ([P, I32, P, P, P, P, P], ctypes.c_int),
+            "gbgpu_bellman_ford": ([P, I32, P, P, P, P], ctypes.c_int),
+            "gbgpu_widest_path": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_multi": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_batch": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_server_create": ([P, ctypes.c_size_t, I32, P, P], ctypes.c_int),
@@ -170,7 +173,7 @@ class Graph:
     :meth:`free` (the library borrows them)."""
 
     def __init__(self, offsets, nbrs, weights=None, validate: bool = True, stream=None,
-                 name: str = ""):
+                 name: str = "", signed_weights: bool = False):
         self.offsets = _dev_tensor(offsets, torch.int64)
         self.nbrs = _dev_tensor(nbrs, torch.int32)
         if self.nbrs.numel() == 0:
@@ -182,7 +185,7 @@ class Graph:
         self.m = int(offsets[-1]) if not isinstance(offsets, torch.Tensor) else int(self.offsets[-1].item())
         self.name = name
         h = ctypes.c_void_p()
-        flags = SYMMETRIC | (VALIDATE if validate else 0)
+        flags = SYMMETRIC | (VALIDATE if validate else 0) | (SIGNED_WEIGHTS if signed_weights else 0)
         _check(lib().gbgpu_load_csr(
             self.n, self.m, ctypes.c_void_p(self.offsets.data_ptr()),
             ctypes.c_void_p(self.nbrs.data_ptr()),
@@ -194,11 +197,12 @@ class Graph:
         self.max_weight = int(mw.value)
 
     @classmethod
-    def from_csr(cls, g, validate: bool = True, with_weights: bool = True, stream=None):
+    def from_csr(cls, g, validate: bool = True, with_weights: bool = True, stream=None,
+                 signed_weights: bool = False):
         """From a host CSR (graphgen.CSR-like object with offsets/nbrs/weights)."""
         w = g.weights if with_weights else None
         return cls(g.offsets, g.nbrs, w, validate=validate, stream=stream,
-                   name=getattr(g, "name", ""))
+                   name=getattr(g, "name", ""), signed_weights=signed_weights)
 
     def free(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -264,6 +268,28 @@ def wbfs(g: Graph, src: int, dist=None, parent=None, opts=None, stream=None,
                             ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats),
                             _stream_ptr(stream)))
     return (dist, parent, st.as_dict()) if stats else (dist, parent)
+
+
+def bellman_ford(g: Graph, src: int, dist=None, opts=None, stream=None, stats: bool = False):
+    """General-weight SSSP.  Returns dist int64[n] (INT64_MAX = unreachable,
+    INT64_MIN = minus infinity behind a reachable negative cycle)."""
+    dist = _out(dist, g.n, torch.int64)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(lib().gbgpu_bellman_ford(g.handle, int(src), ctypes.c_void_p(dist.data_ptr()), oref,
+                                    _st_ref(st, stats), _stream_ptr(stream)))
+    return (dist, st.as_dict()) if stats else dist
+
+
+def widest_path(g: Graph, src: int, width=None, opts=None, stream=None, stats: bool = False):
+    """Widest (bottleneck) path.  Returns int32 storage holding the uint32
+    widths (source 0xFFFFFFFF, unreachable 0); use ``as_u32`` to view."""
+    width = _out(width, g.n, torch.int32)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(lib().gbgpu_widest_path(g.handle, int(src), ctypes.c_void_p(width.data_ptr()), oref,
+                                   _st_ref(st, stats), _stream_ptr(stream)))
+    return (width, st.as_dict()) if stats else width
 
 
 def bfs_multi(g: Graph, srcs: Sequence[int], dist=None, parent=None, opts=None, stream=None,

@@ -30,24 +30,6 @@
 
 namespace gb {
 
-constexpr int kLogCap = 8192;
-
-struct BfsWs {
-    int64_t n = 0;
-    int64_t nwords = 0;
-    uint32_t* V = nullptr;
-    uint32_t* F[3] = {nullptr, nullptr, nullptr};
-    uint32_t* Q[2] = {nullptr, nullptr};
-    uint32_t* P[2] = {nullptr, nullptr};
-    unsigned long long* ctl = nullptr;  // qcnt[4], qover[4] at +4/+8, end reported at +12,
-                                        // reached counts at +14/+15, totals at +64
-    HostLog hl;                         // progress words + round log (host memory)
-    uint32_t last_rounds = 0;           // rounds of the last BFS on this workspace
-    void* block = nullptr;              // owned device block (NULL when borrowed)
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t done = nullptr;          // after the last launch of the last run
-};
-
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t bfs_ws_bytes(int64_t n, int64_t nwords) {

@@ -60,6 +60,7 @@ struct gbgpu_graph_s {
     const int32_t* nbr = nullptr;
     const int32_t* w = nullptr;
     int32_t maxw = 0;
+    int32_t minw = 1;            // smallest weight when one is below 1, else 1
     int64_t nwords = 0;          // bitmap words, padded to a multiple of 2 (64 vertices)
     uint32_t* deg = nullptr;     // owned: degree of each vertex
     uint32_t* pruned = nullptr;  // owned: bit set for vertices of degree 0 or 1 and padding
@@ -79,6 +80,7 @@ struct gbgpu_graph_s {
                                  // degree 1, ascending by vertex
     uint32_t nleaf = 0;
     gb::BfsWs* bfs = nullptr;
+    gb::BfsWs* sr = nullptr;     // workspace of the Bellman-Ford / widest-path rounds
     gb::WbfsWs* wbfs = nullptr;
     gb::MultiWs* multi = nullptr;
 };
@@ -119,6 +121,25 @@ struct HostLog {
     uint32_t* d = nullptr;  // device address of the same memory
 };
 constexpr size_t kHostLogOff = 16;
+
+// Workspace of the frontier-round traversals (BFS rounds in bfs.hip; the
+// Bellman-Ford / widest-path rounds in sr.hip use one of their own).
+constexpr int kLogCap = 8192;  // rounds kept in the pinned round log
+struct BfsWs {
+    int64_t n = 0;
+    int64_t nwords = 0;
+    uint32_t* V = nullptr;
+    uint32_t* F[3] = {nullptr, nullptr, nullptr};
+    uint32_t* Q[2] = {nullptr, nullptr};
+    uint32_t* P[2] = {nullptr, nullptr};
+    unsigned long long* ctl = nullptr;  // qcnt[4], qover[4] at +4/+8, end reported at +12,
+                                        // reached counts at +14/+15, totals at +64
+    HostLog hl;                         // progress words + round log (host memory)
+    uint32_t last_rounds = 0;           // rounds of the last run on this workspace
+    void* block = nullptr;              // owned device block (NULL when borrowed)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t done = nullptr;          // after the last launch of the last run
+};
 int host_log_alloc(HostLog* hl, size_t log_steps);
 void host_log_free(HostLog* hl);
 

@@ -149,7 +149,6 @@ enum : uint32_t {
     VF_ORDER = 4u,
     VF_SELF = 8u,
     VF_ASYM = 16u,
-    VF_WEIGHT = 32u,
     VF_WASYM = 64u,
 };
 
@@ -177,13 +176,22 @@ __device__ int64_t find_in_list(const int64_t* off, const int32_t* nbr, int64_t 
     return -1;
 }
 
+// Weight range: *maxw = largest weight (when >= 1), *below = largest 1 - w
+// over weights below 1 (0 when every weight is >= 1).
+__device__ __forceinline__ void note_weight_range(int32_t lmax, uint32_t lbelow, int32_t* maxw,
+                                                  uint32_t* below) {
+    if (lmax > 0) atomicMax(maxw, lmax);
+    if (lbelow) atomicMax(below, lbelow);
+}
+
 __global__ void check_edges_kernel(const int64_t* off, const int32_t* nbr, const int32_t* w,
-                                   int64_t n, uint32_t* flag, int32_t* maxw) {
+                                   int64_t n, uint32_t* flag, int32_t* maxw, uint32_t* below) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; u < n; u += stride) {
         int32_t prev = -1;
         int32_t lmax = 0;
+        uint32_t lbelow = 0;
         for (int64_t e = off[u]; e < off[u + 1]; ++e) {
             int32_t v = nbr[e];
             if (v < 0 || v >= n) { atomicOr(flag, VF_RANGE); continue; }
@@ -193,22 +201,30 @@ __global__ void check_edges_kernel(const int64_t* off, const int32_t* nbr, const
             int64_t back = find_in_list(off, nbr, v, (int32_t)u);
             if (back < 0) atomicOr(flag, VF_ASYM);
             if (w) {
-                if (w[e] < 1) atomicOr(flag, VF_WEIGHT);
                 if (back >= 0 && w[back] != w[e]) atomicOr(flag, VF_WASYM);
                 lmax = max(lmax, w[e]);
+                if (w[e] < 1) lbelow = max(lbelow, (uint32_t)(1 - (int64_t)w[e]));
             }
         }
-        if (w && lmax > 0) atomicMax(maxw, lmax);
+        if (w) note_weight_range(lmax, lbelow, maxw, below);
     }
 }
 
-__global__ void max_weight_kernel(const int32_t* w, int64_t m, int32_t* maxw) {
+__global__ void weight_range_kernel(const int32_t* w, int64_t m, int32_t* maxw, uint32_t* below) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int32_t lm = 0;
-    for (; e < m; e += stride) lm = max(lm, w[e]);
-    for (int d = 32; d >= 1; d >>= 1) lm = max(lm, __shfl_xor(lm, d, 64));
-    if (lane_id() == 0 && lm > 0) atomicMax(maxw, lm);
+    uint32_t lb = 0;
+    for (; e < m; e += stride) {
+        const int32_t x = w[e];
+        lm = max(lm, x);
+        if (x < 1) lb = max(lb, (uint32_t)(1 - (int64_t)x));
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        lm = max(lm, __shfl_xor(lm, d, 64));
+        lb = max(lb, (uint32_t)__shfl_xor(lb, d, 64));
+    }
+    if (lane_id() == 0) note_weight_range(lm, lb, maxw, below);
 }
 
 // Degrees, the bitmap of vertices of degree <= 1, and the head of every
@@ -403,7 +419,7 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         g->num_cus = cus;
-    uint32_t* scratch = nullptr;  // [0] flag, [1] max weight
+    uint32_t* scratch = nullptr;  // [0] flag, [1] max weight, [2] largest 1 - w below 1
     auto fail = [&](int st) {
         if (g->deg) (void)hipFree(g->deg);
         if (g->pruned) (void)hipFree(g->pruned);
@@ -430,8 +446,9 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
                                            "offsets[0] != 0 or offsets[n] != m)"));
         if (m > 0) {
             hipLaunchKernelGGL(check_edges_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, offsets,
-                               neighbors, weights, n, scratch, (int32_t*)(scratch + 1));
-            if (hipMemcpyAsync(host, scratch, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                               neighbors, weights, n, scratch, (int32_t*)(scratch + 1),
+                               scratch + 2);
+            if (hipMemcpyAsync(host, scratch, 12, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return fail(set_error(GBGPU_E_HIP, "edge validation failed to run"));
             uint32_t f = host[0];
@@ -440,18 +457,21 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
                 return fail(set_error(GBGPU_E_INVALID, "adjacency list not strictly ascending"));
             if (f & VF_SELF) return fail(set_error(GBGPU_E_INVALID, "self loop"));
             if (f & VF_ASYM) return fail(set_error(GBGPU_E_INVALID, "graph is not symmetric"));
-            if (f & VF_WEIGHT) return fail(set_error(GBGPU_E_INVALID, "weight < 1"));
             if (f & VF_WASYM) return fail(set_error(GBGPU_E_INVALID, "weights are not symmetric"));
         }
     } else if (weights && m > 0) {
-        hipLaunchKernelGGL(max_weight_kernel, dim3(grid_for(m)), dim3(kBlock), 0, s, weights, m,
-                           (int32_t*)(scratch + 1));
-        if (hipMemcpyAsync(host, scratch, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipLaunchKernelGGL(weight_range_kernel, dim3(grid_for(m)), dim3(kBlock), 0, s, weights, m,
+                           (int32_t*)(scratch + 1), scratch + 2);
+        if (hipMemcpyAsync(host, scratch, 12, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
-            return fail(set_error(GBGPU_E_HIP, "max weight kernel failed"));
+            return fail(set_error(GBGPU_E_HIP, "weight range kernel failed"));
     }
     g->maxw = weights ? (int32_t)host[1] : 0;
-    if (weights && m > 0 && g->maxw < 1) return fail(set_error(GBGPU_E_INVALID, "weight < 1"));
+    g->minw = (weights && m > 0 && host[2]) ? (int32_t)(1 - (int64_t)host[2]) : 1;
+    if (g->minw < 1 && !(flags & GBGPU_SIGNED_WEIGHTS))
+        return fail(set_error(GBGPU_E_INVALID,
+                              "weight %d < 1 (load with GBGPU_SIGNED_WEIGHTS for general-weight "
+                              "SSSP)", g->minw));
     hipLaunchKernelGGL(degree_kernel, dim3(grid_for(std::max<int64_t>(n, g->nwords))), dim3(kBlock),
                        0, s, offsets, neighbors, n, g->nwords, g->deg, g->pruned, g->head);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
@@ -469,6 +489,7 @@ int gbgpu_graph_free(gbgpu_graph g) {
     {
         std::lock_guard<std::mutex> lk(g->mu);
         free_bfs_ws(g->bfs);
+        free_bfs_ws(g->sr);
         free_wbfs_ws(g->wbfs);
         free_multi_ws(g->multi);
         if (g->plan) (void)hipFree(g->plan);
@@ -506,6 +527,7 @@ int gbgpu_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, cons
                gbgpu_stats* st, void* stream) {
     if (!g) return set_error(GBGPU_E_INVALID, "graph is NULL");
     if (!g->w) return set_error(GBGPU_E_INVALID, "graph was loaded without weights");
+    if (g->minw < 1) return set_error(GBGPU_E_INVALID, "weighted BFS needs weights >= 1");
     if (!dist || !parent) return set_error(GBGPU_E_INVALID, "dist/parent is NULL");
     if (src < 0 || src >= g->n)
         return set_error(GBGPU_E_INVALID, "src %d out of range [0, %lld)", src, (long long)g->n);

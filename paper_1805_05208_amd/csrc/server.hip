@@ -371,6 +371,7 @@ int gbgpu_submit(gbgpu_server sv, const gbgpu_query* q, uint64_t* ticket) {
     if (!q->dist || !q->parent) return set_error(GBGPU_E_INVALID, "NULL output");
     if (q->kind == GBGPU_QUERY_WBFS) {
         if (!g->w) return set_error(GBGPU_E_INVALID, "graph has no weights");
+        if (g->minw < 1) return set_error(GBGPU_E_INVALID, "weighted BFS needs weights >= 1");
         if (g->maxw > 2047) return set_error(GBGPU_E_UNSUPPORTED, "max weight exceeds 2047");
         if ((uint64_t)std::max(g->maxw, 1) * (uint64_t)g->n >= 0xFFFFFFFEull)
             return set_error(GBGPU_E_OVERFLOW, "max_weight * n must stay below 2^32 - 2");
