@@ -371,6 +371,23 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         extra["wbfs_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
         extra["wbfs_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
         log(f"wBFS rmat: {extra['wbfs_rmat24_gteps']} GTEPS, {extra['wbfs_rmat24_ms']} ms/source")
+        # general-weight SSSP (Bellman-Ford rounds) and widest path on the
+        # same weighted graph and sources (edges of the reached component,
+        # as for wBFS)
+        for key, fn, reached in (
+                ("bellman_ford", gb.bellman_ford, lambda x: x.cpu().numpy() != 2**63 - 1),
+                ("widest_path", gb.widest_path, lambda x: gb.as_u32(x) != 0)):
+            tot_e, tot_t, rounds = 0, 0.0, 0
+            for s in srcs[:4]:
+                x, st = fn(Gw, s, stats=True)
+                rounds += st["rounds"]
+                tot_e += int(deg[reached(x)].sum()) // 2
+                tot_t += timed(lambda: fn(Gw, s, opts=user_opts), reps=2)
+            extra[f"{key}_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
+            extra[f"{key}_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
+            extra[f"{key}_rmat24_rounds"] = round(rounds / 4, 1)
+            log(f"{key} rmat: {extra[f'{key}_rmat24_gteps']} GTEPS, "
+                f"{extra[f'{key}_rmat24_ms']} ms/source, {rounds / 4:.1f} rounds")
         # batched: 64 sources in one call vs one at a time
         s64 = [int(x) for x in gg.sources(g, 64, seed=3)]
         tb = timed(lambda: gb.bfs_multi(G, s64), reps=2)
@@ -394,6 +411,12 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         extra["torus256_bfs_gteps"] = round(tg.m / 2 / tt / 1e9, 3)
         extra["torus256_wbfs_ms"] = round(tw * 1e3, 3)
         log(f"torus: BFS {extra['torus256_bfs_ms']} ms, wBFS {extra['torus256_wbfs_ms']} ms")
+        tbf = timed(lambda: gb.bellman_ford(T, ts, opts=user_opts), reps=1)
+        twp = timed(lambda: gb.widest_path(T, ts, opts=user_opts), reps=1)
+        extra["torus256_bellman_ford_ms"] = round(tbf * 1e3, 3)
+        extra["torus256_widest_path_ms"] = round(twp * 1e3, 3)
+        log(f"torus: Bellman-Ford {extra['torus256_bellman_ford_ms']} ms, "
+            f"widest path {extra['torus256_widest_path_ms']} ms")
         # batched on the high-diameter graph: 64 sources in one call against
         # the same 64 one at a time (4 timed, scaled)
         t64 = [int(x) for x in gg.sources(tg, 64, seed=3)]

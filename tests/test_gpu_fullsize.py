@@ -5,7 +5,12 @@
   (w < 24) from the first, element by element against the oracle; two rows
   of a 64-source batch against the oracle;
 * 256^3 torus: BFS against the closed form of distances and min-ID parents,
-  weighted BFS (w < 24) against the definition-level checks.
+  weighted BFS (w < 24) against the definition-level checks;
+* general-weight SSSP and widest path (w < 24) from the first timed source:
+  RMAT-24 against the oracle's Bellman-Ford and widest path, the torus
+  against the oracle's Dial distances (equal to Bellman-Ford's on
+  positive weights; its own passes would number in the hundreds there) and
+  widest path.
 """
 import json
 import os
@@ -98,4 +103,30 @@ def test_torus256(gb):
     assert_same(d.cpu().numpy(), p.cpu().numpy(), ed, ep, "torus256 bfs")
     wd, wp = gb.wbfs(G, s, opts=tuned(prefix, "wbfs"))
     check_wbfs(g, s, gb.as_u32(wd), wp.cpu().numpy())
+    G.free()
+
+
+def test_rmat24_bellman_ford_and_widest_path(gb, rmat24):
+    g, w, G = rmat24
+    s = int(gg.sources(g, 16, seed=3)[0])
+    d = gb.bellman_ford(G, s).cpu().numpy()
+    ref = oracle.bellman_ford(g, s, w)
+    bad = np.nonzero(d != ref)[0]
+    assert bad.size == 0, f"bellman-ford: {bad.size} mismatches, first v={bad[0]}"
+    wd = gb.as_u32(gb.widest_path(G, s))
+    wref = oracle.widest_path(g, s, w)
+    bad = np.nonzero(wd != wref)[0]
+    assert bad.size == 0, f"widest path: {bad.size} mismatches, first v={bad[0]}"
+
+
+def test_torus256_bellman_ford_and_widest_path(gb):
+    g = gg.torus3d(256).with_weights(24, seed=2)
+    G = gb.Graph.from_csr(g, validate=False)
+    s = int(gg.sources(g, 1, seed=3)[0])
+    d = gb.bellman_ford(G, s).cpu().numpy()
+    dd, _ = oracle.wbfs(g, s)
+    exp = np.where(dd == oracle.WBFS_INF, np.int64(2**63 - 1), dd.astype(np.int64))
+    assert np.array_equal(d, exp)
+    wd = gb.as_u32(gb.widest_path(G, s))
+    assert np.array_equal(wd, oracle.widest_path(g, s))
     G.free()
