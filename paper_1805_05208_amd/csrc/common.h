@@ -76,6 +76,7 @@ struct gbgpu_graph_s {
     uint32_t* core = nullptr;    // owned: ids of the vertices of degree >= 2, ascending
     uint4* core_head = nullptr;  // owned: their head records, in the same order
     uint32_t ncore = 0;
+    int64_t max_degree = 0;      // set with the vertex lists
     uint2* leaf = nullptr;       // owned: (vertex, its one neighbour) for every vertex of
                                  // degree 1, ascending by vertex
     uint32_t nleaf = 0;

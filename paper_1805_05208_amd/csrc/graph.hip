@@ -314,8 +314,10 @@ int ensure_pull_plan(gbgpu_graph g) {
     std::vector<uint32_t> corev;
     std::vector<uint2> leafv;
     corev.reserve((size_t)n);
+    int64_t maxd = 0;
     for (int64_t v = 0; v < n; ++v) {
         const int64_t d = off[v + 1] - off[v];
+        maxd = std::max(maxd, d);
         if (d >= 2) corev.push_back((uint32_t)v);
         else if (d == 1) leafv.push_back(make_uint2((uint32_t)v, 0u));
     }
@@ -370,6 +372,7 @@ int ensure_pull_plan(gbgpu_graph g) {
     g->plan = d_items;
     g->nplan = (uint32_t)items.size();
     g->core = d_core;
+    g->max_degree = maxd;
     g->core_head = d_core_head;
     g->ncore = (uint32_t)corev.size();
     g->leaf = d_leaf;
