@@ -20,6 +20,8 @@ Path Problems"), with parents fixed by the minimum-ID rule:
   cycle), textbook Bellman-Ford.
 * :func:`widest_path` -- widest (bottleneck) path widths (uint32, source =
   0xFFFFFFFF, unreachable = 0), Dijkstra on a max-heap of widths.
+* :func:`betweenness` -- single-source betweenness dependencies (float64,
+  0 for the source and unreachable vertices), textbook Brandes.
 """
 from __future__ import annotations
 
@@ -65,6 +67,8 @@ def _load():
         lib.oracle_bellman_ford.restype = ctypes.c_int
         lib.oracle_widest_path.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P]
         lib.oracle_widest_path.restype = ctypes.c_int
+        lib.oracle_betweenness.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P]
+        lib.oracle_betweenness.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -139,3 +143,13 @@ def widest_path(g, src: int, weights=None):
     if rc != 0:
         raise ValueError(f"oracle_widest_path failed with code {rc}")
     return width
+
+
+def betweenness(g, src: int):
+    """Return dep float64[n]: S[v] = sum over targets t of sigma_st(v) / sigma_st."""
+    off, nb = _csr_arrays(g)
+    dep = np.empty(g.n, dtype=np.float64)
+    rc = _load().oracle_betweenness(g.n, _p(off), _p(nb), int(src), _p(dep))
+    if rc != 0:
+        raise ValueError(f"oracle_betweenness failed with code {rc}")
+    return dep

@@ -33,6 +33,13 @@
  *         lowers a distance (at most n - 1), one more pass to find the
  *         vertices a negative cycle still lowers, then every vertex reachable
  *         from those gets minus infinity.
+ *   Single-source betweenness: S[v] = sum over targets t != src, v of
+ *         sigma_st(v) / sigma_st (sigma_st = number of shortest src-t paths,
+ *         sigma_st(v) = those through v), double; S[src] = 0 and S = 0 for
+ *         unreachable vertices.  Textbook Brandes: a FIFO BFS counting
+ *         shortest paths, then dependencies accumulated in reverse BFS order,
+ *         delta(v) = sum over children w of sigma(v) / sigma(w) * (1 +
+ *         delta(w)).
  *   Widest path: W[v] = maximum over src-v paths of the smallest weight on
  *         the path (weights >= 1, uint32).  The source's width is that of the
  *         empty path, 0xFFFFFFFF; an unreachable vertex gets 0, the maximum
@@ -358,5 +365,58 @@ int oracle_widest_path(int64_t n, const int64_t* offsets, const int32_t* nbrs,
     free(h.v);
     free(h.pos);
     free(done);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-source betweenness centrality (Brandes).                          */
+/* ------------------------------------------------------------------------ */
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
+int oracle_betweenness(int64_t n, const int64_t* offsets, const int32_t* nbrs, int32_t src,
+                       double* dep) {
+    if (n <= 0 || src < 0 || src >= n) return -1;
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* d = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    double* sigma = (double*)calloc((size_t)n, sizeof(double));
+    if (!order || !d || !sigma) {
+        free(order);
+        free(d);
+        free(sigma);
+        return -2;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        d[v] = -1;
+        dep[v] = 0.0;
+    }
+    /* FIFO BFS; a vertex's path count is complete when it is dequeued,
+     * since all its predecessors were dequeued before it */
+    int64_t head = 0, tail = 0;
+    d[src] = 0;
+    sigma[src] = 1.0;
+    order[tail++] = src;
+    while (head < tail) {
+        const int32_t v = order[head++];
+        for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) {
+            const int32_t w = nbrs[e];
+            if (d[w] < 0) {
+                d[w] = d[v] + 1;
+                order[tail++] = w;
+            }
+            if (d[w] == d[v] + 1) sigma[w] += sigma[v];
+        }
+    }
+    /* reverse BFS order: every child of v is finished before v */
+    for (int64_t i = tail - 1; i >= 0; --i) {
+        const int32_t w = order[i];
+        for (int64_t e = offsets[w]; e < offsets[w + 1]; ++e) {
+            const int32_t v = nbrs[e];
+            if (d[v] == d[w] - 1) dep[v] += sigma[v] / sigma[w] * (1.0 + dep[w]);
+        }
+    }
+    dep[src] = 0.0;
+    free(order);
+    free(d);
+    free(sigma);
     return 0;
 }
