@@ -202,6 +202,25 @@ int gbgpu_bellman_ford(gbgpu_graph g, int32_t src, int64_t* dist, const gbgpu_op
 int gbgpu_widest_path(gbgpu_graph g, int32_t src, uint32_t* width, const gbgpu_opts* o,
                       gbgpu_stats* st, void* stream);
 
+/* Single-source betweenness centrality (Betweenness Centrality problem
+ * statement; the paper's algorithm box after Brandes: a forward pass of BFS
+ * rounds counting shortest paths with fetch-and-add, then a backward pass
+ * over the levels accumulating dependencies).
+ *   src     source vertex in [0, n)
+ *   dep     dev double[n] output: S[v] = sum over targets t (t != src,
+ *           t != v) of sigma_st(v) / sigma_st, where sigma_st counts the
+ *           shortest src-t paths and sigma_st(v) those through v; 0 for src
+ *           and for unreachable vertices.  Path counts and sums are fp64 and
+ *           the additions run in an order the device's atomics decide, so
+ *           results agree with a sequential evaluation to rounding.
+ *   o, st   optional (NULL allowed); st->rounds = number of BFS levels,
+ *           st->reached = vertices reached
+ * Weights, when present, are ignored (unweighted shortest paths).
+ * Errors: E_INVALID for a null handle/output or src out of range.  The call
+ * returns when dep is complete. */
+int gbgpu_bc(gbgpu_graph g, int32_t src, double* dep, const gbgpu_opts* o, gbgpu_stats* st,
+             void* stream);
+
 /* Batched multi-source BFS on one graph: k independent BFS problems solved
  * together with one 64-bit frontier mask per vertex and group of 64 sources.
  *   srcs    host int32[k], each in [0, n) (repeats allowed)

@@ -27,6 +27,7 @@ WBFS_INF = 0xFFFFFFFF
 EXPORTED = [
     "gbgpu_last_error", "gbgpu_version", "gbgpu_load_csr", "gbgpu_graph_free",
     "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bellman_ford", "gbgpu_widest_path",
+    "gbgpu_bc",
     "gbgpu_bfs_multi", "gbgpu_bfs_batch",
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
@@ -101,6 +102,7 @@ def lib() -> ctypes.CDLL:
             "gbgpu_wbfs": ([P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bellman_ford": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_widest_path": ([P, I32, P, P, P, P], ctypes.c_int),
+            "gbgpu_bc": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_multi": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_batch": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_server_create": ([P, ctypes.c_size_t, I32, P, P], ctypes.c_int),
@@ -290,6 +292,17 @@ def widest_path(g: Graph, src: int, width=None, opts=None, stream=None, stats: b
     _check(lib().gbgpu_widest_path(g.handle, int(src), ctypes.c_void_p(width.data_ptr()), oref,
                                    _st_ref(st, stats), _stream_ptr(stream)))
     return (width, st.as_dict()) if stats else width
+
+
+def betweenness(g: Graph, src: int, dep=None, opts=None, stream=None, stats: bool = False):
+    """Single-source betweenness dependencies, float64[n] (0 for src and
+    for unreachable vertices)."""
+    dep = _out(dep, g.n, torch.float64)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(lib().gbgpu_bc(g.handle, int(src), ctypes.c_void_p(dep.data_ptr()), oref,
+                          _st_ref(st, stats), _stream_ptr(stream)))
+    return (dep, st.as_dict()) if stats else dep
 
 
 def bfs_multi(g: Graph, srcs: Sequence[int], dist=None, parent=None, opts=None, stream=None,

@@ -47,6 +47,9 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 struct BfsWs;
 // Workspace of the weighted BFS (wbfs.hip).
 struct WbfsWs;
+// Workspace of betweenness centrality (bc.hip).
+struct BcWs;
+void free_bc_ws(BcWs* w);
 // Workspace of multi-source BFS (multi.hip).
 struct MultiWs;
 
@@ -82,6 +85,7 @@ struct gbgpu_graph_s {
     uint32_t nleaf = 0;
     gb::BfsWs* bfs = nullptr;
     gb::BfsWs* sr = nullptr;     // workspace of the Bellman-Ford / widest-path rounds
+    gb::BcWs* bc = nullptr;      // workspace of betweenness centrality
     gb::WbfsWs* wbfs = nullptr;
     gb::MultiWs* multi = nullptr;
 };

@@ -493,6 +493,7 @@ int gbgpu_graph_free(gbgpu_graph g) {
         std::lock_guard<std::mutex> lk(g->mu);
         free_bfs_ws(g->bfs);
         free_bfs_ws(g->sr);
+        free_bc_ws(g->bc);
         free_wbfs_ws(g->wbfs);
         free_multi_ws(g->multi);
         if (g->plan) (void)hipFree(g->plan);
