@@ -388,6 +388,17 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
             extra[f"{key}_rmat24_rounds"] = round(rounds / 4, 1)
             log(f"{key} rmat: {extra[f'{key}_rmat24_gteps']} GTEPS, "
                 f"{extra[f'{key}_rmat24_ms']} ms/source, {rounds / 4:.1f} rounds")
+        # single-source betweenness (forward + backward pass over the BFS
+        # levels; every edge of the reached component is visited twice)
+        tot_e, tot_t = 0, 0.0
+        for s in srcs[:4]:
+            x, st = gb.betweenness(G, s, stats=True)
+            d, _ = gb.bfs(G, s)
+            tot_e += int(deg[d.cpu().numpy() != 2**31 - 1].sum()) // 2
+            tot_t += timed(lambda: gb.betweenness(G, s), reps=2)
+        extra["bc_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
+        extra["bc_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
+        log(f"betweenness rmat: {extra['bc_rmat24_ms']} ms/source, {extra['bc_rmat24_gteps']} GTEPS")
         # batched: 64 sources in one call vs one at a time
         s64 = [int(x) for x in gg.sources(g, 64, seed=3)]
         tb = timed(lambda: gb.bfs_multi(G, s64), reps=2)
@@ -415,10 +426,13 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         # threshold the relaxation rounds choose for themselves)
         tbf = timed(lambda: gb.bellman_ford(T, ts), reps=1)
         twp = timed(lambda: gb.widest_path(T, ts), reps=1)
+        tbc = timed(lambda: gb.betweenness(T, ts), reps=1)
+        extra["torus256_bc_ms"] = round(tbc * 1e3, 3)
         extra["torus256_bellman_ford_ms"] = round(tbf * 1e3, 3)
         extra["torus256_widest_path_ms"] = round(twp * 1e3, 3)
         log(f"torus: Bellman-Ford {extra['torus256_bellman_ford_ms']} ms, "
-            f"widest path {extra['torus256_widest_path_ms']} ms")
+            f"widest path {extra['torus256_widest_path_ms']} ms, "
+            f"betweenness {extra['torus256_bc_ms']} ms")
         # batched on the high-diameter graph: 64 sources in one call against
         # the same 64 one at a time (4 timed, scaled)
         t64 = [int(x) for x in gg.sources(tg, 64, seed=3)]

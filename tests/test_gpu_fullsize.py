@@ -10,7 +10,9 @@
   RMAT-24 against the oracle's Bellman-Ford and widest path, the torus
   against the oracle's Dial distances (equal to Bellman-Ford's on
   positive weights; its own passes would number in the hundreds there) and
-  widest path.
+  widest path;
+* single-source betweenness from the first timed source, RMAT-24 and torus,
+  against the oracle within the tolerance of test_gpu_bc.py.
 """
 import json
 import os
@@ -130,3 +132,22 @@ def test_torus256_bellman_ford_and_widest_path(gb):
     wd = gb.as_u32(gb.widest_path(G, s))
     assert np.array_equal(wd, oracle.widest_path(g, s))
     G.free()
+
+
+@pytest.mark.parametrize("which", ["rmat24", "torus256"])
+def test_betweenness(gb, which, request):
+    from test_gpu_bc import assert_close, rtol_for
+    if which == "rmat24":
+        g, _, G = request.getfixturevalue("rmat24")
+        s = int(gg.sources(g, 16, seed=3)[0])
+        own = False
+    else:
+        g = gg.torus3d(256)
+        G = gb.Graph.from_csr(g, validate=False, with_weights=False)
+        s = int(gg.sources(g, 1, seed=3)[0])
+        own = True
+    dep, st = gb.betweenness(G, s, stats=True)
+    exp = oracle.betweenness(g, s)
+    assert_close(dep.cpu().numpy(), exp, rtol_for(g, st["rounds"]), f"{which} src={s}")
+    if own:
+        G.free()
