@@ -45,6 +45,7 @@ struct BcWs {
     uint32_t* degO = nullptr;    // their degrees (+ a trailing 0)
     uint32_t* P = nullptr;       // exclusive prefix of degO
     uint32_t* Pb = nullptr;      // sorted level keys, then P at every level boundary
+    uint32_t* res = nullptr;     // level mod 3 of every vertex, 2 bits (3 = unreached)
     double* sigma = nullptr;
     double* acc = nullptr;
     void* scan_tmp = nullptr;
@@ -70,7 +71,8 @@ static int ensure_bc_ws(gbgpu_graph g) {
     if (g->bc) return GBGPU_OK;
     const int64_t n = g->n;
     const size_t u32n = a256((size_t)(n + 64) * 4), f64n = a256((size_t)n * 8);
-    const size_t total = 2 * u32n + 5 * u32n + 2 * f64n;
+    const size_t resn = a256((size_t)(n / 16 + 64) * 4);
+    const size_t total = 2 * u32n + 5 * u32n + resn + 2 * f64n;
     BcWs* w = new BcWs();
     hipError_t e = hipMalloc(&w->block, total);
     if (e != hipSuccess) {
@@ -86,6 +88,7 @@ static int ensure_bc_ws(gbgpu_graph g) {
     w->degO = (uint32_t*)p; p += u32n;
     w->P = (uint32_t*)p; p += u32n;
     w->Pb = (uint32_t*)p; p += u32n;
+    w->res = (uint32_t*)p; p += resn;
     w->sigma = (double*)p; p += f64n;
     w->acc = (double*)p;
     size_t tb = 0, ts = 0;
@@ -144,6 +147,30 @@ __global__ void bc_bounds_kernel(const uint32_t* P, const uint32_t* base, int32_
     if (i <= levels) Pb[i] = P[base[i]];
 }
 
+// Neighbours' levels differ by at most one, so level mod 3 tells a vertex's
+// parents (level - 1), peers and children (level + 1) apart.  Packed 16
+// vertices to a word, the residues take n / 4 bytes: the per-edge test reads
+// them instead of the 4-byte distances, and they fit in the L2.
+__global__ __launch_bounds__(kBlock) void bc_residue_kernel(const int32_t* dist, int64_t n,
+                                                            uint32_t* res) {
+    const int64_t words = (n + 15) / 16;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t wd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; wd < words; wd += stride) {
+        uint32_t x = 0u;
+        for (int i = 0; i < 16; ++i) {
+            const int64_t v = wd * 16 + i;
+            uint32_t r = 3u;
+            if (v < n && dist[v] != INT32_MAX) r = (uint32_t)dist[v] % 3u;
+            x |= r << (2 * i);
+        }
+        res[wd] = x;
+    }
+}
+
+__device__ __forceinline__ uint32_t level_res(const uint32_t* res, uint32_t u) {
+    return (res[u >> 4] >> ((u & 15u) * 2u)) & 3u;
+}
+
 __global__ __launch_bounds__(kBlock) void bc_init_kernel(double* sigma, double* acc, int64_t n,
                                                          int32_t src) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -164,12 +191,12 @@ __global__ __launch_bounds__(kBlock) void bc_output_kernel(const double* sigma, 
 struct BcArgs {
     const int64_t* off;
     const int32_t* nbr;
-    const int32_t* dist;
+    const uint32_t* res;  // level mod 3, packed
     const uint32_t* Q;   // this level's vertices
     const uint32_t* P;   // their absolute degree prefix
     uint32_t cnt;
     uint32_t e0, e1;     // this level's absolute edge range
-    int32_t level;
+    uint32_t want;       // residue of the neighbours this pass reads
     uint32_t chunk;
     double* sigma;
     double* acc;
@@ -183,7 +210,8 @@ __device__ __forceinline__ double shfl_down_f64(double x, int d) {
 }
 
 // Per edge (v, u) of a level-l vertex v: forward, sigma(u) when u is on
-// level l-1; backward, 1 / sigma(u) + acc(u) when u is on level l+1.  The
+// level l-1; backward, 1 / sigma(u) + acc(u) when u is on level l+1 (told
+// apart by the level residues).  The
 // lanes of one v are contiguous in a window; their sum goes to v with one
 // atomic.
 template <bool kForward>
@@ -199,11 +227,8 @@ struct BcPolicy {
         const uint32_t owner = act ? v : 0xFFFFFFFFu;
         if (act) {
             const uint32_t u = (uint32_t)a->nbr[e];
-            if (kForward) {
-                if (a->dist[u] == a->level - 1) c = a->sigma[u];
-            } else {
-                if (a->dist[u] == a->level + 1) c = 1.0 / a->sigma[u] + a->acc[u];
-            }
+            if (level_res(a->res, u) == a->want)
+                c = kForward ? a->sigma[u] : 1.0 / a->sigma[u] + a->acc[u];
         }
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
@@ -294,6 +319,8 @@ int gbgpu_bc(gbgpu_graph g, int32_t src, double* dep, const gbgpu_opts* o, gbgpu
                        w->cnt, levels, w->Pb);
     std::vector<uint32_t> pb((size_t)levels + 1);
     GB_HIP(hipMemcpyAsync(pb.data(), w->Pb, ((size_t)levels + 1) * 4, hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(bc_residue_kernel, dim3(grid_n((g->n + 15) / 16)), dim3(kBlock), 0, s,
+                       w->dist, g->n, w->res);
     hipLaunchKernelGGL(bc_init_kernel, dim3(grid_n(g->n)), dim3(kBlock), 0, s, w->sigma, w->acc,
                        g->n, src);
     GB_HIP(hipGetLastError());
@@ -302,7 +329,7 @@ int gbgpu_bc(gbgpu_graph g, int32_t src, double* dep, const gbgpu_opts* o, gbgpu
     BcArgs a;
     a.off = g->off;
     a.nbr = g->nbr;
-    a.dist = w->dist;
+    a.res = w->res;
     a.sigma = w->sigma;
     a.acc = w->acc;
     int64_t launches = 0;
@@ -312,7 +339,7 @@ int gbgpu_bc(gbgpu_graph g, int32_t src, double* dep, const gbgpu_opts* o, gbgpu
         a.cnt = cnt[(size_t)l];
         a.e0 = pb[(size_t)l];
         a.e1 = pb[(size_t)l + 1];
-        a.level = l;
+        a.want = (uint32_t)((fwd ? l + 2 : l + 1) % 3);  // (l - 1) mod 3 / (l + 1) mod 3
         if (a.cnt == 0 || a.e1 == a.e0) return GBGPU_OK;
         const uint32_t E = a.e1 - a.e0;
         const uint32_t nw = (uint32_t)opt.grid * kRWaves;
