@@ -22,6 +22,11 @@ Path Problems"), with parents fixed by the minimum-ID rule:
   0xFFFFFFFF, unreachable = 0), Dijkstra on a max-heap of widths.
 * :func:`betweenness` -- single-source betweenness dependencies (float64,
   0 for the source and unreachable vertices), textbook Brandes.
+* :func:`ldd` -- low-diameter decomposition clusters (int32 centre ids),
+  the paper's LDD rounds with geometric shifts from SplitMix64 and the
+  smallest-ID-claimer rule; :func:`geo_shifts` returns the shifts.
+* :func:`components` -- connected components, labelled by their smallest
+  vertex id.
 """
 from __future__ import annotations
 
@@ -47,7 +52,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c (plain C, -O2, single-threaded) into liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -69,6 +74,16 @@ def _load():
         lib.oracle_widest_path.restype = ctypes.c_int
         lib.oracle_betweenness.argtypes = [ctypes.c_int64, P, P, ctypes.c_int32, P]
         lib.oracle_betweenness.restype = ctypes.c_int
+        lib.oracle_geo_threshold.argtypes = [ctypes.c_double]
+        lib.oracle_geo_threshold.restype = ctypes.c_uint64
+        lib.oracle_geo_shift.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_uint64]
+        lib.oracle_geo_shift.restype = ctypes.c_int32
+        lib.oracle_ldd.argtypes = [ctypes.c_int64, P, P, ctypes.c_double, ctypes.c_uint64,
+                                   ctypes.c_uint32, P]
+        lib.oracle_ldd.restype = ctypes.c_int
+        lib.oracle_components.argtypes = [ctypes.c_int64, P, P, P]
+        lib.oracle_components.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -153,3 +168,31 @@ def betweenness(g, src: int):
     if rc != 0:
         raise ValueError(f"oracle_betweenness failed with code {rc}")
     return dep
+
+
+def geo_shifts(n: int, beta: float, seed: int, level: int = 0) -> np.ndarray:
+    """The LDD shifts g(v) (int32[n])."""
+    L = _load()
+    thr = L.oracle_geo_threshold(float(beta))
+    return np.array([L.oracle_geo_shift(seed, level, v, thr) for v in range(n)], dtype=np.int32)
+
+
+def ldd(g, beta: float, seed: int, level: int = 0):
+    """Return cluster int32[n] (centre id of every vertex's cluster)."""
+    off, nb = _csr_arrays(g)
+    cl = np.empty(g.n, dtype=np.int32)
+    rc = _load().oracle_ldd(g.n, _p(off), _p(nb), float(beta), int(seed) & (2**64 - 1),
+                            int(level), _p(cl))
+    if rc != 0:
+        raise ValueError(f"oracle_ldd failed with code {rc}")
+    return cl
+
+
+def components(g):
+    """Return label int32[n] = smallest vertex id of each vertex's component."""
+    off, nb = _csr_arrays(g)
+    lab = np.empty(g.n, dtype=np.int32)
+    rc = _load().oracle_components(g.n, _p(off), _p(nb), _p(lab))
+    if rc != 0:
+        raise ValueError(f"oracle_components failed with code {rc}")
+    return lab

@@ -41,7 +41,19 @@
  *         delta(v) = sum over children w of sigma(v) / sigma(w) * (1 +
  *         delta(w)).
  *   Widest path: W[v] = maximum over src-v paths of the smallest weight on
- *         the path (weights >= 1, uint32).  The source's width is that of the
+ *         the path (weights >= 1, uint32).
+ *   Low-diameter decomposition (Miller-Peng-Xu, the paper's LDD algorithm
+ *         box): every vertex draws a shift g(v); start(v) = max g - g(v);
+ *         rounds r = 0, 1, ...: unvisited vertices with start(v) = r become
+ *         centres of their own clusters and join the frontier, then the
+ *         frontier claims its unvisited neighbours, which take the cluster of
+ *         their smallest-ID frontier neighbour and form the next frontier.
+ *         The shifts are the floored Exp(beta) shifts of the box, drawn as
+ *         geometric variables: g(v) = number of leading SplitMix64 draws
+ *         below q * 2^64, q = exp(-beta), counter seed ^ (level << 40 |
+ *         v << 6 | i), at most 63.
+ *   Connectivity: label[v] = smallest vertex id of v's component (a FIFO
+ *         BFS from each unlabelled vertex in increasing id order).  The source's width is that of the
  *         empty path, 0xFFFFFFFF; an unreachable vertex gets 0, the maximum
  *         over no paths (the statement's "infinity when unreachable" would
  *         collide with the source's own width).  Textbook method: Dijkstra's
@@ -50,6 +62,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 #define BFS_INF INT32_MAX
 #define WBFS_INF 0xFFFFFFFFu
@@ -418,5 +431,132 @@ int oracle_betweenness(int64_t n, const int64_t* offsets, const int32_t* nbrs, i
     free(order);
     free(d);
     free(sigma);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Low-diameter decomposition and connectivity.                             */
+/* ------------------------------------------------------------------------ */
+
+/* SplitMix64 output function (Steele, Lea and Flood, "Fast splittable
+ * pseudorandom number generators", 2014, with the constants of Vigna's
+ * reference code), applied to a counter. */
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+/* q * 2^64 with q = exp(-beta): a draw below it is a success. */
+uint64_t oracle_geo_threshold(double beta) {
+    const double q = exp(-beta);
+    if (q >= 1.0) return UINT64_MAX;
+    return (uint64_t)ldexp(q, 64);
+}
+
+int32_t oracle_geo_shift(uint64_t seed, uint32_t level, uint32_t v, uint64_t thr) {
+    int32_t g = 0;
+    while (g < 63 &&
+           splitmix64(seed ^ (((uint64_t)level << 40) | ((uint64_t)v << 6) | (uint64_t)g)) < thr)
+        ++g;
+    return g;
+}
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
+int oracle_ldd(int64_t n, const int64_t* offsets, const int32_t* nbrs, double beta,
+               uint64_t seed, uint32_t level, int32_t* cluster) {
+    if (n <= 0 || !(beta > 0.0)) return -1;
+    const uint64_t thr = oracle_geo_threshold(beta);
+    int32_t* start = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* par = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* F = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* nxt = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t* bstart = (int64_t*)calloc(65, sizeof(int64_t));
+    int32_t* byst = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!start || !par || !F || !nxt || !bstart || !byst) {
+        free(start); free(par); free(F); free(nxt); free(bstart); free(byst);
+        return -2;
+    }
+    int32_t gmax = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        start[v] = oracle_geo_shift(seed, level, (uint32_t)v, thr);
+        if (start[v] > gmax) gmax = start[v];
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        start[v] = gmax - start[v];
+        cluster[v] = -1;
+        par[v] = -1;
+        bstart[start[v] + 1]++;
+    }
+    /* vertices listed by start round */
+    for (int i = 1; i <= 64; ++i) bstart[i] += bstart[i - 1];
+    {
+        int64_t fill[64];
+        for (int i = 0; i < 64; ++i) fill[i] = bstart[i];
+        for (int64_t v = 0; v < n; ++v) byst[fill[start[v]]++] = (int32_t)v;
+    }
+    int64_t visited = 0, nf = 0;
+    for (int64_t r = 0; visited < n; ++r) {
+        /* new centres: still unvisited vertices whose start round is r */
+        if (r <= gmax) {
+            for (int64_t i = bstart[r]; i < bstart[r + 1]; ++i) {
+                const int32_t v = byst[i];
+                if (cluster[v] < 0) {
+                    cluster[v] = v;
+                    F[nf++] = v;
+                }
+            }
+        }
+        visited += nf;
+        /* the frontier claims its unvisited neighbours; each takes the
+         * cluster of its smallest-ID frontier neighbour */
+        int64_t nn = 0;
+        for (int64_t i = 0; i < nf; ++i) {
+            const int32_t u = F[i];
+            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+                const int32_t d = nbrs[e];
+                if (cluster[d] >= 0) continue;
+                if (par[d] < 0) {
+                    par[d] = u;
+                    nxt[nn++] = d;
+                } else if (u < par[d]) {
+                    par[d] = u;
+                }
+            }
+        }
+        for (int64_t i = 0; i < nn; ++i) cluster[nxt[i]] = cluster[par[nxt[i]]];
+        int32_t* t = F;
+        F = nxt;
+        nxt = t;
+        nf = nn;
+    }
+    free(start); free(par); free(F); free(nxt); free(bstart); free(byst);
+    return 0;
+}
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure. */
+int oracle_components(int64_t n, const int64_t* offsets, const int32_t* nbrs, int32_t* label) {
+    if (n <= 0) return -1;
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!queue) return -2;
+    for (int64_t v = 0; v < n; ++v) label[v] = -1;
+    for (int64_t s = 0; s < n; ++s) {
+        if (label[s] >= 0) continue;
+        int64_t head = 0, tail = 0;
+        label[s] = (int32_t)s;
+        queue[tail++] = (int32_t)s;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            for (int64_t e = offsets[u]; e < offsets[u + 1]; ++e) {
+                const int32_t v = nbrs[e];
+                if (label[v] < 0) {
+                    label[v] = (int32_t)s;
+                    queue[tail++] = v;
+                }
+            }
+        }
+    }
+    free(queue);
     return 0;
 }
