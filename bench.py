@@ -399,6 +399,15 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         extra["bc_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
         extra["bc_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
         log(f"betweenness rmat: {extra['bc_rmat24_ms']} ms/source, {extra['bc_rmat24_gteps']} GTEPS")
+        # low-diameter decomposition and connectivity (beta 0.2): whole graph
+        for key, fn in (("ldd", gb.ldd), ("connectivity", gb.connectivity)):
+            _, st = fn(G, 0.2, 1, stats=True)
+            t = timed(lambda: fn(G, 0.2, 1), reps=3)
+            extra[f"{key}_rmat24_ms"] = round(t * 1e3, 3)
+            extra[f"{key}_rmat24_gteps"] = round(g.m / 2 / t / 1e9, 2)
+            extra[f"{key}_rmat24_rounds"] = st["rounds"]
+            log(f"{key} rmat: {extra[f'{key}_rmat24_ms']} ms, {extra[f'{key}_rmat24_gteps']} GTEPS, "
+                f"{st['rounds']} rounds/levels, {st['reached']} clusters/components")
         # batched: 64 sources in one call vs one at a time
         s64 = [int(x) for x in gg.sources(g, 64, seed=3)]
         tb = timed(lambda: gb.bfs_multi(G, s64), reps=2)
@@ -427,6 +436,10 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         tbf = timed(lambda: gb.bellman_ford(T, ts), reps=1)
         twp = timed(lambda: gb.widest_path(T, ts), reps=1)
         tbc = timed(lambda: gb.betweenness(T, ts), reps=1)
+        for key, fn in (("ldd", gb.ldd), ("connectivity", gb.connectivity)):
+            t = timed(lambda: fn(T, 0.2, 1), reps=2)
+            extra[f"torus256_{key}_ms"] = round(t * 1e3, 3)
+            log(f"torus: {key} {extra[f'torus256_{key}_ms']} ms")
         extra["torus256_bc_ms"] = round(tbc * 1e3, 3)
         extra["torus256_bellman_ford_ms"] = round(tbf * 1e3, 3)
         extra["torus256_widest_path_ms"] = round(twp * 1e3, 3)

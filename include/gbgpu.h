@@ -221,6 +221,44 @@ int gbgpu_widest_path(gbgpu_graph g, int32_t src, uint32_t* width, const gbgpu_o
 int gbgpu_bc(gbgpu_graph g, int32_t src, double* dep, const gbgpu_opts* o, gbgpu_stats* st,
              void* stream);
 
+/* Low-diameter decomposition (the paper's LDD algorithm box after Miller,
+ * Peng and Xu, "Connectivity Problems" section).  Vertex v draws a shift
+ * g(v); with start(v) = max g - g(v), round r first makes every unvisited
+ * vertex with start(v) = r the centre of its own cluster, then the frontier
+ * claims its unvisited neighbours.  Deterministic form of the algorithm:
+ *   - g(v) = number of leading SplitMix64 outputs (Steele, Lea and Flood
+ *     2014) of the counters seed ^ (v << 6 | i), i = 0, 1, ..., that lie
+ *     below exp(-beta) * 2^64, at most 63 (the integer part of an
+ *     Exp(beta) shift, which is what the rounds use);
+ *   - a vertex claimed by several frontier vertices in one round joins the
+ *     cluster of the one with the smallest id.
+ *   beta    in (0, 1): larger beta, smaller clusters and more cut edges
+ *   seed    any 64-bit value
+ *   cluster dev int32[n] output: the centre vertex of v's cluster
+ *   o, st   optional (NULL allowed); st->rounds = rounds run, st->reached =
+ *           number of clusters
+ * Weights, when present, are ignored.  Errors: E_INVALID for a null
+ * handle/output or beta outside (0, 1).  The call returns when cluster is
+ * complete. */
+int gbgpu_ldd(gbgpu_graph g, double beta, uint64_t seed, int32_t* cluster,
+              const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
+/* Connected components (Connectivity problem statement; the paper's
+ * connectivity algorithm box: an LDD, every cluster contracted to one vertex
+ * with the edges between clusters kept once and those inside dropped, then
+ * the same on the contracted graph until it has no edges, and the labels
+ * mapped back).  Recursion level l draws its shifts from the counters
+ * seed ^ (l << 40 | v << 6 | i).
+ *   label   dev int32[n] output: the smallest vertex id of v's component
+ *   o, st   optional (NULL allowed); st->rounds = recursion levels,
+ *           st->reached = number of components
+ * Labels do not depend on beta or seed (only the running time does).
+ * Weights, when present, are ignored.  Errors: E_INVALID for a null
+ * handle/output or beta outside (0, 1); E_NOMEM when a level's buffers
+ * (about 16 bytes per stored edge) cannot be allocated. */
+int gbgpu_connectivity(gbgpu_graph g, double beta, uint64_t seed, int32_t* label,
+                       const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
 /* Batched multi-source BFS on one graph: k independent BFS problems solved
  * together with one 64-bit frontier mask per vertex and group of 64 sources.
  *   srcs    host int32[k], each in [0, n) (repeats allowed)

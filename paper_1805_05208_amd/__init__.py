@@ -27,7 +27,7 @@ WBFS_INF = 0xFFFFFFFF
 EXPORTED = [
     "gbgpu_last_error", "gbgpu_version", "gbgpu_load_csr", "gbgpu_graph_free",
     "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bellman_ford", "gbgpu_widest_path",
-    "gbgpu_bc",
+    "gbgpu_bc", "gbgpu_ldd", "gbgpu_connectivity",
     "gbgpu_bfs_multi", "gbgpu_bfs_batch",
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
             "gbgpu_bellman_ford": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_widest_path": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_bc": ([P, I32, P, P, P, P], ctypes.c_int),
+            "gbgpu_ldd": ([P, ctypes.c_double, ctypes.c_uint64, P, P, P, P], ctypes.c_int),
+            "gbgpu_connectivity": ([P, ctypes.c_double, ctypes.c_uint64, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_multi": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_batch": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_server_create": ([P, ctypes.c_size_t, I32, P, P], ctypes.c_int),
@@ -303,6 +305,32 @@ def betweenness(g: Graph, src: int, dep=None, opts=None, stream=None, stats: boo
     _check(lib().gbgpu_bc(g.handle, int(src), ctypes.c_void_p(dep.data_ptr()), oref,
                           _st_ref(st, stats), _stream_ptr(stream)))
     return (dep, st.as_dict()) if stats else dep
+
+
+def ldd(g: Graph, beta: float = 0.2, seed: int = 0, cluster=None, opts=None, stream=None,
+        stats: bool = False):
+    """Low-diameter decomposition: int32[n] centre id of every vertex's
+    cluster (stats: rounds, reached = number of clusters)."""
+    cluster = _out(cluster, g.n, torch.int32)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(lib().gbgpu_ldd(g.handle, float(beta), int(seed) & (2**64 - 1),
+                           ctypes.c_void_p(cluster.data_ptr()), oref, _st_ref(st, stats),
+                           _stream_ptr(stream)))
+    return (cluster, st.as_dict()) if stats else cluster
+
+
+def connectivity(g: Graph, beta: float = 0.2, seed: int = 0, label=None, opts=None, stream=None,
+                 stats: bool = False):
+    """Connected components: int32[n] smallest vertex id of every vertex's
+    component (stats: rounds = recursion levels, reached = components)."""
+    label = _out(label, g.n, torch.int32)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(lib().gbgpu_connectivity(g.handle, float(beta), int(seed) & (2**64 - 1),
+                                    ctypes.c_void_p(label.data_ptr()), oref, _st_ref(st, stats),
+                                    _stream_ptr(stream)))
+    return (label, st.as_dict()) if stats else label
 
 
 def bfs_multi(g: Graph, srcs: Sequence[int], dist=None, parent=None, opts=None, stream=None,

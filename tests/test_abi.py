@@ -29,7 +29,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["gbgpu_load_csr", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_submit", "gbgpu_poll",
                      "gbgpu_bfs_multi", "gbgpu_bfs_batch", "gbgpu_last_error",
-                     "gbgpu_bellman_ford", "gbgpu_widest_path", "gbgpu_bc"]:
+                     "gbgpu_bellman_ford", "gbgpu_widest_path", "gbgpu_bc",
+                     "gbgpu_ldd", "gbgpu_connectivity"]:
         assert required in names
 
 

@@ -12,7 +12,9 @@
   positive weights; its own passes would number in the hundreds there) and
   widest path;
 * single-source betweenness from the first timed source, RMAT-24 and torus,
-  against the oracle within the tolerance of test_gpu_bc.py.
+  against the oracle within the tolerance of test_gpu_bc.py;
+* low-diameter decomposition (beta 0.2, the seed the benchmark uses) and
+  connectivity, RMAT-24 and torus, element by element against the oracle.
 """
 import json
 import os
@@ -149,5 +151,26 @@ def test_betweenness(gb, which, request):
     dep, st = gb.betweenness(G, s, stats=True)
     exp = oracle.betweenness(g, s)
     assert_close(dep.cpu().numpy(), exp, rtol_for(g, st["rounds"]), f"{which} src={s}")
+    if own:
+        G.free()
+
+
+@pytest.mark.parametrize("which", ["rmat24", "torus256"])
+def test_ldd_and_connectivity(gb, which, request):
+    if which == "rmat24":
+        g, _, G = request.getfixturevalue("rmat24")
+        own = False
+    else:
+        g = gg.torus3d(256)
+        G = gb.Graph.from_csr(g, validate=False, with_weights=False)
+        own = True
+    cl = gb.ldd(G, 0.2, 1).cpu().numpy()
+    exp = oracle.ldd(g, 0.2, 1)
+    bad = np.nonzero(cl != exp)[0]
+    assert bad.size == 0, f"{which} LDD: {bad.size} differ, first v={bad[0]}"
+    lab = gb.connectivity(G, 0.2, 1).cpu().numpy()
+    exp = oracle.components(g)
+    bad = np.nonzero(lab != exp)[0]
+    assert bad.size == 0, f"{which} connectivity: {bad.size} differ, first v={bad[0]}"
     if own:
         G.free()
