@@ -50,6 +50,8 @@ struct WbfsWs;
 // Workspace of betweenness centrality (bc.hip).
 struct BcWs;
 void free_bc_ws(BcWs* w);
+struct Arena;
+void free_arena(Arena* a);
 // Workspace of multi-source BFS (multi.hip).
 struct MultiWs;
 
@@ -86,6 +88,7 @@ struct gbgpu_graph_s {
     gb::BfsWs* bfs = nullptr;
     gb::BfsWs* sr = nullptr;     // workspace of the Bellman-Ford / widest-path rounds
     gb::BcWs* bc = nullptr;      // workspace of betweenness centrality
+    gb::Arena* cc = nullptr;     // device arena of the LDD / connectivity calls
     gb::WbfsWs* wbfs = nullptr;
     gb::MultiWs* multi = nullptr;
 };

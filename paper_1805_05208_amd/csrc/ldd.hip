@@ -53,62 +53,117 @@ static uint64_t geo_threshold(double beta) {
     return (uint64_t)std::ldexp(q, 64);
 }
 
-struct LddWs {
-    int64_t n = 0;
-    unsigned long long* key = nullptr;  // (claimer id << 32 | cluster), kUnclaimed
-    uint32_t* vis = nullptr;            // visited bitmap (frontiers of earlier rounds)
-    uint32_t* F[2] = {nullptr, nullptr};  // frontier bitmaps (current, next)
-    uint32_t* start = nullptr;          // start round of every vertex
-    uint32_t* byst = nullptr;           // vertices ordered by start round
-    uint32_t* keys_sorted = nullptr;    // sort scratch
-    uint32_t* Q[2] = {nullptr, nullptr};
-    uint32_t* P[2] = {nullptr, nullptr};
-    unsigned long long* ctl = nullptr;  // qcnt[2], qover[2], gmax, bucket bounds at +8, totals at +128
-    void* tmp = nullptr;
-    size_t tmp_bytes = 0;
-    void* block = nullptr;
+// Device arena of the LDD and connectivity calls, cached on the graph
+// handle: a stack (each recursion level releases what it took), so one
+// allocation serves every level; what does not fit comes from hipMalloc for
+// the rest of the call, and the next call starts with an arena as large as
+// this call's peak.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, top = 0, peak = 0;
+    std::vector<void*> extra;
 };
 
-static void free_ldd_ws(LddWs* w) {
-    if (!w) return;
-    if (w->tmp) (void)hipFree(w->tmp);
-    if (w->block) (void)hipFree(w->block);
-    delete w;
+void free_arena(Arena* a) {
+    if (!a) return;
+    if (a->base) (void)hipFree(a->base);
+    for (void* p : a->extra) (void)hipFree(p);
+    delete a;
 }
 
 static size_t b256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int new_ldd_ws(int64_t n, LddWs** out) {
-    LddWs* w = new LddWs();
-    w->n = n;
+// Readies the graph's arena for a call expected to need `need` bytes.
+static int arena_begin(gbgpu_graph g, size_t need, Arena** out) {
+    if (!g->cc) g->cc = new Arena();
+    Arena* a = g->cc;
+    need = std::max(need, a->peak);
+    if (a->cap < need) {
+        if (a->base) (void)hipFree(a->base);
+        a->base = nullptr;
+        a->cap = 0;
+        if (hipMalloc(&a->base, need) != hipSuccess) {
+            a->base = nullptr;
+            return set_error(GBGPU_E_NOMEM, "LDD/connectivity arena of %zu bytes", need);
+        }
+        a->cap = need;
+    }
+    a->top = 0;
+    *out = a;
+    return GBGPU_OK;
+}
+
+// Ends a call: the overflow allocations go (the stream has been synchronised).
+static void arena_end(Arena* a) {
+    for (void* p : a->extra) (void)hipFree(p);
+    a->extra.clear();
+    a->top = 0;
+}
+
+template <typename T>
+static int arena_alloc(Arena& a, size_t count, T** p) {
+    const size_t bytes = b256(std::max<size_t>(count, 1) * sizeof(T));
+    a.peak = std::max(a.peak, a.top + bytes);
+    if (a.top + bytes <= a.cap) {
+        *p = (T*)(a.base + a.top);
+        a.top += bytes;
+        return GBGPU_OK;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess)
+        return set_error(GBGPU_E_NOMEM, "LDD/connectivity buffer of %zu bytes", bytes);
+    a.extra.push_back(q);
+    *p = (T*)q;
+    return GBGPU_OK;
+}
+
+// A CSR as the rounds read it (the input graph or a contracted one).
+struct GView {
+    int64_t n, m;
+    const int64_t* off;
+    const int32_t* nbr;
+    const uint32_t* deg;
+};
+
+struct LddWs {
+    unsigned long long* key;  // (claimer id << 32 | cluster), kUnclaimed
+    uint32_t* vis;            // visited bitmap (frontiers of earlier rounds)
+    uint32_t* F[2];           // frontier bitmaps (current, next)
+    uint32_t* start;          // start round of every vertex
+    uint32_t* byst;           // vertices ordered by start round
+    uint32_t* keys_sorted;    // sort scratch
+    uint32_t* Q[2];
+    uint32_t* P[2];
+    unsigned long long* ctl;  // qcnt[2], qover[2], gmax, bucket bounds at +8, totals at +128
+    void* tmp;
+    size_t tmp_bytes;
+};
+
+static size_t ldd_ws_bytes(int64_t n) {
     const int64_t nwords = ((n + 63) / 64) * 2;
-    const size_t u32n = b256((size_t)(n + 64) * 4);
-    const size_t total = b256((size_t)n * 8) + 3 * b256((size_t)nwords * 4) + 7 * u32n +
-                         b256((128 + kSpread * kSpreadStride) * 8);
-    if (hipMalloc(&w->block, total) != hipSuccess) {
-        delete w;
-        return set_error(GBGPU_E_NOMEM, "LDD workspace of %zu bytes", total);
-    }
-    char* p = (char*)w->block;
-    w->key = (unsigned long long*)p; p += b256((size_t)n * 8);
-    w->vis = (uint32_t*)p; p += b256((size_t)nwords * 4);
-    for (int i = 0; i < 2; ++i) { w->F[i] = (uint32_t*)p; p += b256((size_t)nwords * 4); }
-    w->start = (uint32_t*)p; p += u32n;
-    w->byst = (uint32_t*)p; p += u32n;
-    w->keys_sorted = (uint32_t*)p; p += u32n;
-    for (int i = 0; i < 2; ++i) { w->Q[i] = (uint32_t*)p; p += u32n; }
-    for (int i = 0; i < 2; ++i) { w->P[i] = (uint32_t*)p; p += u32n; }
-    w->ctl = (unsigned long long*)p;
+    return b256((size_t)n * 8) + 3 * b256((size_t)nwords * 4) + 7 * b256((size_t)(n + 64) * 4) +
+           b256((128 + kSpread * kSpreadStride) * 8) + b256((size_t)n * 8) + (1u << 20);
+}
+
+static int new_ldd_ws(Arena& A, int64_t n, LddWs* w) {
+    const int64_t nwords = ((n + 63) / 64) * 2;
+    GB_TRY(arena_alloc(A, (size_t)n, &w->key));
+    GB_TRY(arena_alloc(A, (size_t)nwords, &w->vis));
+    for (int i = 0; i < 2; ++i) GB_TRY(arena_alloc(A, (size_t)nwords, &w->F[i]));
+    GB_TRY(arena_alloc(A, (size_t)n + 64, &w->start));
+    GB_TRY(arena_alloc(A, (size_t)n + 64, &w->byst));
+    GB_TRY(arena_alloc(A, (size_t)n + 64, &w->keys_sorted));
+    for (int i = 0; i < 2; ++i) GB_TRY(arena_alloc(A, (size_t)n + 64, &w->Q[i]));
+    for (int i = 0; i < 2; ++i) GB_TRY(arena_alloc(A, (size_t)n + 64, &w->P[i]));
+    GB_TRY(arena_alloc(A, (size_t)(128 + kSpread * kSpreadStride), &w->ctl));
     size_t ts = 0;
-    if (rocprim::radix_sort_pairs(nullptr, ts, w->start, w->keys_sorted,
-                                  rocprim::counting_iterator<uint32_t>(0u), w->byst,
-                                  (unsigned int)n, 0u, 6u) != hipSuccess ||
-        hipMalloc(&w->tmp, std::max<size_t>(ts, 256)) != hipSuccess) {
-        free_ldd_ws(w);
-        return set_error(GBGPU_E_NOMEM, "LDD sort workspace");
-    }
+    GB_HIP(rocprim::radix_sort_pairs(nullptr, ts, w->start, w->keys_sorted,
+                                     rocprim::counting_iterator<uint32_t>(0u), w->byst,
+                                     (unsigned int)n, 0u, 6u));
     w->tmp_bytes = std::max<size_t>(ts, 256);
-    *out = w;
+    char* t = nullptr;
+    GB_TRY(arena_alloc(A, w->tmp_bytes, &t));
+    w->tmp = t;
     return GBGPU_OK;
 }
 
@@ -416,9 +471,9 @@ static int gridn(int64_t items) {
 }
 
 // One LDD of g into cluster[] (centre ids).  Returns the rounds run.
-static int run_ldd(gbgpu_graph g, double beta, uint64_t seed, uint32_t level, int32_t* cluster,
+static int run_ldd(const GView& g, double beta, uint64_t seed, uint32_t level, int32_t* cluster,
                    const gbgpu_opts& o, hipStream_t s, LddWs* w, int32_t* rounds_out) {
-    const int64_t n = g->n;
+    const int64_t n = g.n;
     const int64_t nwords = ((n + 63) / 64) * 2;
     GB_HIP(hipMemsetAsync(w->ctl, 0, 128 * 8, s));
     hipLaunchKernelGGL(ldd_shift_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, n, nwords, seed, level,
@@ -436,16 +491,16 @@ static int run_ldd(gbgpu_graph g, double beta, uint64_t seed, uint32_t level, in
     GB_HIP(hipStreamSynchronize(s));
     const uint32_t gmax = (uint32_t)hc[4];
     const int igrid = (int)std::max<int64_t>(1, std::min<int64_t>(n / (4 * kRBlock), o.grid));
-    const int64_t work = std::max<int64_t>(1, std::max<int64_t>(n / kRBlock, g->m / 4096));
+    const int64_t work = std::max<int64_t>(1, std::max<int64_t>(n / kRBlock, g.m / 4096));
     const int egrid = (int)std::min<int64_t>(work, o.grid);
     // After round gmax's injection every vertex is in a cluster (a vertex
     // still unvisited at round start(v) becomes a centre then), so the rounds
     // are exactly 0..gmax and the last needs no expansion.
     for (uint32_t r = 0; r <= gmax; ++r) {
         LddArgs a;
-        a.off = g->off;
-        a.nbr = g->nbr;
-        a.deg = g->deg;
+        a.off = g.off;
+        a.nbr = g.nbr;
+        a.deg = g.deg;
         a.key = w->key;
         a.vis = w->vis;
         a.Fc = w->F[r & 1];
@@ -466,7 +521,7 @@ static int run_ldd(gbgpu_graph g, double beta, uint64_t seed, uint32_t level, in
         a.n = (uint32_t)n;
         a.dense_at = o.force_direction == 1   ? ~0ull
                      : o.force_direction == 2 ? 0ull
-                                              : (uint64_t)(g->m / std::max(1, o.tau));
+                                              : (uint64_t)(g.m / std::max(1, o.tau));
         a.light = (uint32_t)o.pull_light;
         hipLaunchKernelGGL(ldd_inject_kernel, dim3(igrid), dim3(kRBlock), 0, s, a);
         if (r < gmax)
@@ -496,15 +551,45 @@ __global__ __launch_bounds__(kBlock) void cc_iota_kernel(int64_t n, const int64_
 // Inter-cluster edges as keys (centre(u) << bits | centre(v)), compacted
 // in any order (they are sorted next): a wavefront appends its keys to the
 // workgroup's LDS buffer, and the workgroup copies the buffer out with one
-// reservation when it is half full.
-constexpr int kKeyCap = 8192;
-constexpr uint32_t kCrossChunk = 256;  // edges per wavefront step: a step adds <= kKeyCap / 2
+// reservation when it is half full.  Most inter-cluster edges repeat a key
+// (a few large clusters share many edges), so each workgroup first drops the
+// keys it has already emitted, found in an LDS hash set (linear probing; a
+// key whose probes all fail is emitted anyway -- the sort and unique that
+// follow remove what duplicates remain).
+constexpr int kKeyCap = 4096;
+constexpr uint32_t kCrossChunk = 128;  // edges per wavefront step: a step adds <= kKeyCap / 2
+constexpr int kHashSlots = 4096;
+constexpr int kHashProbes = 8;
 
 struct KeyBuf {
     unsigned long long k[kKeyCap];
+    unsigned long long set[kHashSlots];
     uint32_t cnt;
     unsigned long long base;
 };
+
+__device__ __forceinline__ unsigned long long shfl_up64(unsigned long long x, int d) {
+    const uint32_t lo = __shfl_up((uint32_t)x, d, 64);
+    const uint32_t hi = __shfl_up((uint32_t)(x >> 32), d, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// true when `key` was not in the set (and is now, if a slot was free)
+__device__ __forceinline__ bool key_first_seen(KeyBuf* b, unsigned long long key) {
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 52);
+#pragma unroll 1
+    for (int p = 0; p < kHashProbes; ++p) {
+        const uint32_t slot = (h + (uint32_t)p) & (kHashSlots - 1);
+        const unsigned long long cur = b->set[slot];
+        if (cur == key) return false;
+        if (cur == kUnclaimed) {
+            const unsigned long long old = atomicCAS(&b->set[slot], kUnclaimed, key);
+            if (old == kUnclaimed) return true;
+            if (old == key) return false;
+        }
+    }
+    return true;
+}
 
 struct CrossPolicy {
     const int32_t* nbr;
@@ -514,13 +599,17 @@ struct CrossPolicy {
     static constexpr bool kSkipDead = false;
     __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
     __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e, bool) {
-        bool take = false;
-        unsigned long long key = 0;
+        bool cross = false;
+        unsigned long long key = kUnclaimed;
         if (act) {
             const uint32_t a = (uint32_t)cluster[u], b = (uint32_t)cluster[nbr[e]];
-            take = a != b;
-            key = ((unsigned long long)a << bits) | b;
+            cross = a != b;
+            if (cross) key = ((unsigned long long)a << bits) | b;
         }
+        // the previous lane's equal key stands for this one (edges of one
+        // vertex are adjacent)
+        const unsigned long long prev = shfl_up64(key, 1);
+        const bool take = cross && (lane_id() == 0 || prev != key) && key_first_seen(buf, key);
         const uint64_t m = ballot(take);
         if (!m) return;
         const int ld = first_lane(m);
@@ -532,15 +621,18 @@ struct CrossPolicy {
     __device__ __forceinline__ void window_done() {}
 };
 
-// Workgroup-uniform: copies the buffered keys to out[] at a reserved range.
+// Workgroup-uniform: copies the buffered keys to out[] at a reserved range
+// (keys past `cap` are counted, not written: the caller then retries with a
+// larger buffer).
 __device__ __forceinline__ void keybuf_flush(KeyBuf& b, unsigned long long* count,
-                                             unsigned long long* out) {
+                                             unsigned long long* out, uint64_t cap) {
     __syncthreads();
     const uint32_t n = b.cnt;
     if (threadIdx.x == 0 && n) b.base = atomicAdd(count, (unsigned long long)n);
     __syncthreads();
     const unsigned long long base = b.base;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[base + i] = b.k[i];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        if (base + i < cap) out[base + i] = b.k[i];
     __syncthreads();
     if (threadIdx.x == 0) b.cnt = 0;
     __syncthreads();
@@ -553,9 +645,11 @@ __global__ __launch_bounds__(kRBlock, 8) void cc_cross_kernel(const uint32_t* io
                                                               const int32_t* cluster,
                                                               uint32_t bits,
                                                               unsigned long long* count,
-                                                              unsigned long long* out) {
+                                                              unsigned long long* out,
+                                                              uint64_t cap) {
     __shared__ KeyBuf buf;
     if (threadIdx.x == 0) buf.cnt = 0;
+    for (int i = threadIdx.x; i < kHashSlots; i += blockDim.x) buf.set[i] = kUnclaimed;
     __syncthreads();
     CrossPolicy pol{nbr, cluster, &buf, bits};
     const uint32_t wave = threadIdx.x / kWave;
@@ -570,9 +664,9 @@ __global__ __launch_bounds__(kRBlock, 8) void cc_cross_kernel(const uint32_t* io
         __syncthreads();
         const uint32_t nb = buf.cnt;
         __syncthreads();  // every thread has read nb before anyone can append again
-        if (nb > (uint32_t)kKeyCap / 2) keybuf_flush(buf, count, out);
+        if (nb > (uint32_t)kKeyCap / 2) keybuf_flush(buf, count, out, cap);
     }
-    keybuf_flush(buf, count, out);
+    keybuf_flush(buf, count, out, cap);
 }
 
 // The contracted graph keeps only the clusters with an edge to another
@@ -668,107 +762,116 @@ __global__ __launch_bounds__(kBlock) void cc_fill_kernel(uint32_t* x, int64_t n,
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = val;
 }
 
-// Device buffers owned by one level of the recursion.
-struct Level {
-    std::vector<void*> bufs;
-    ~Level() {
-        for (void* p : bufs) (void)hipFree(p);
-    }
-    template <typename T>
-    int alloc(T** p, size_t count) {
-        void* q = nullptr;
-        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
-            return set_error(GBGPU_E_NOMEM, "connectivity buffer of %zu bytes", count * sizeof(T));
-        bufs.push_back(q);
-        *p = (T*)q;
-        return GBGPU_OK;
-    }
-};
+__global__ __launch_bounds__(kBlock) void cc_deg_kernel(const int64_t* off, int64_t n,
+                                                        uint32_t* deg) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        deg[v] = (uint32_t)(off[v + 1] - off[v]);
+}
 
 // label[v] for the vertices of g: a vertex of v's component, so equal
 // exactly when connected.  levels_out accumulates the recursion depth.
-static int connect_rec(gbgpu_graph g, double beta, uint64_t seed, uint32_t level, int32_t* label,
-                       const gbgpu_opts& o, hipStream_t s, int32_t* levels_out) {
-    const int64_t n = g->n;
+// Everything this level takes from the arena is released on return.
+static int connect_rec(const GView& g, double beta, uint64_t seed, uint32_t level,
+                       int32_t* label, const gbgpu_opts& o, hipStream_t s, Arena& A,
+                       int32_t* levels_out) {
+    const int64_t n = g.n;
     *levels_out = (int32_t)level + 1;
     // A level leaves the graph as it is only when every edge joins two
     // vertices of equal shift; fresh shifts per level make a long run of
     // such levels vanishingly unlikely, and this bound turns one into an
     // error instead of unbounded recursion.
     if (level >= 256) return set_error(GBGPU_E_HIP, "connectivity did not converge");
-    Level L;
+    const size_t mark = A.top;
+    struct Release {
+        Arena& A;
+        size_t mark;
+        ~Release() { A.top = mark; }
+    } release{A, mark};
     int32_t* cluster = nullptr;
-    GB_TRY(L.alloc(&cluster, (size_t)n));
+    GB_TRY(arena_alloc(A, (size_t)n, &cluster));
     {
-        LddWs* w = nullptr;
-        GB_TRY(new_ldd_ws(n, &w));
-        std::unique_ptr<LddWs, void (*)(LddWs*)> wg(w, free_ldd_ws);
-        GB_TRY(run_ldd(g, beta, seed, level, cluster, o, s, w, nullptr));
+        const size_t m2 = A.top;
+        LddWs w;
+        GB_TRY(new_ldd_ws(A, n, &w));
+        GB_TRY(run_ldd(g, beta, seed, level, cluster, o, s, &w, nullptr));
+        A.top = m2;  // later kernels on the stream reuse the memory after the LDD's
     }
     auto clusters_are_components = [&]() -> int {
         GB_HIP(hipMemcpyAsync(label, cluster, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
         GB_HIP(hipStreamSynchronize(s));
         return GBGPU_OK;
     };
-    if (g->m == 0) return clusters_are_components();
-    // every edge's key, then the inter-cluster ones compacted
+    if (g.m == 0) return clusters_are_components();
+    // the inter-cluster edges as keys, most duplicates already dropped
     uint32_t *iota = nullptr, *off32 = nullptr;
-    GB_TRY(L.alloc(&iota, (size_t)n));
-    GB_TRY(L.alloc(&off32, (size_t)n + 1));
-    hipLaunchKernelGGL(cc_iota_kernel, dim3(gridn(n + 1)), dim3(kBlock), 0, s, n, g->off, iota, off32);
+    GB_TRY(arena_alloc(A, (size_t)n, &iota));
+    GB_TRY(arena_alloc(A, (size_t)n + 1, &off32));
+    hipLaunchKernelGGL(cc_iota_kernel, dim3(gridn(n + 1)), dim3(kBlock), 0, s, n, g.off, iota, off32);
     uint32_t bits = 1;
     while (bits < 32 && (1ll << bits) < n) ++bits;
-    unsigned long long *keys = nullptr, *cnt = nullptr;
-    GB_TRY(L.alloc(&keys, (size_t)g->m));
-    GB_TRY(L.alloc(&cnt, 2));
-    GB_HIP(hipMemsetAsync(cnt, 0, 16, s));
-    const uint32_t m32 = (uint32_t)g->m;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(g->m / 4096, o.grid));
-    hipLaunchKernelGGL(cc_cross_kernel, dim3(grid), dim3(kRBlock), 0, s, iota, off32, g->off,
-                       (uint32_t)n, m32, g->nbr, cluster, bits, cnt, keys);
-    GB_HIP(hipGetLastError());
-    unsigned long long hm = 0;
-    GB_HIP(hipMemcpyAsync(&hm, cnt, 8, hipMemcpyDeviceToHost, s));
-    GB_HIP(hipStreamSynchronize(s));
-    const uint32_t cross = (uint32_t)hm;
+    unsigned long long* cnt = nullptr;
+    GB_TRY(arena_alloc(A, 2, &cnt));
+    const uint32_t m32 = (uint32_t)g.m;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.m / 4096, o.grid));
+    uint64_t cap = (uint64_t)std::min<int64_t>(g.m, std::max<int64_t>(1 << 20, g.m / 64));
+    unsigned long long* keys = nullptr;
+    uint32_t cross = 0;
+    for (;;) {
+        const size_t mk = A.top;
+        GB_TRY(arena_alloc(A, (size_t)cap, &keys));
+        GB_HIP(hipMemsetAsync(cnt, 0, 16, s));
+        hipLaunchKernelGGL(cc_cross_kernel, dim3(grid), dim3(kRBlock), 0, s, iota, off32, g.off,
+                           (uint32_t)n, m32, g.nbr, cluster, bits, cnt, keys, cap);
+        GB_HIP(hipGetLastError());
+        unsigned long long hm = 0;
+        GB_HIP(hipMemcpyAsync(&hm, cnt, 8, hipMemcpyDeviceToHost, s));
+        GB_HIP(hipStreamSynchronize(s));
+        if (hm <= cap) {
+            cross = (uint32_t)hm;
+            break;
+        }
+        A.top = mk;  // too small: once more with room for every key
+        cap = hm;
+    }
     if (cross == 0) return clusters_are_components();
     // sort and de-duplicate: the contracted edges
     unsigned long long* keys2 = nullptr;
-    GB_TRY(L.alloc(&keys2, (size_t)cross));
-    size_t ts = 0, tu = 0;
+    GB_TRY(arena_alloc(A, (size_t)cross, &keys2));
+    size_t ts = 0, tu = 0, tscan = 0;
     GB_HIP(rocprim::radix_sort_keys(nullptr, ts, keys, keys2, cross, 0u, 2u * bits, s));
     GB_HIP(rocprim::unique(nullptr, tu, keys2, keys, cnt + 1, (size_t)cross,
                            rocprim::equal_to<unsigned long long>(), s));
-    const size_t tmax = std::max(ts, tu);
+    uint32_t *flag = nullptr, *pos = nullptr;
+    GB_HIP(rocprim::exclusive_scan(nullptr, tscan, flag, pos, 0u, (size_t)cross + 1,
+                                   rocprim::plus<uint32_t>(), s));
+    const size_t tmax = std::max(std::max(ts, tu), tscan);
     char* tmp = nullptr;
-    GB_TRY(L.alloc(&tmp, tmax));
+    GB_TRY(arena_alloc(A, tmax, &tmp));
     size_t tsz = tmax;
     GB_HIP(rocprim::radix_sort_keys(tmp, tsz, keys, keys2, cross, 0u, 2u * bits, s));
     tsz = tmax;
     GB_HIP(rocprim::unique(tmp, tsz, keys2, keys, cnt + 1, (size_t)cross,
                            rocprim::equal_to<unsigned long long>(), s));
+    unsigned long long hm = 0;
     GB_HIP(hipMemcpyAsync(&hm, cnt + 1, 8, hipMemcpyDeviceToHost, s));
     GB_HIP(hipStreamSynchronize(s));
     const uint32_t mm = (uint32_t)hm;
     // contracted vertices: the centres with an inter-cluster edge, in order
-    uint32_t *flag = nullptr, *pos = nullptr, *map = nullptr, *rep = nullptr;
+    uint32_t *map = nullptr, *rep = nullptr, *deg2 = nullptr;
     int64_t* off2 = nullptr;
-    int32_t* nbr2 = nullptr;
-    GB_TRY(L.alloc(&flag, (size_t)mm + 1));
-    GB_TRY(L.alloc(&pos, (size_t)mm + 1));
-    GB_TRY(L.alloc(&map, (size_t)n));
-    GB_TRY(L.alloc(&rep, (size_t)mm));
-    GB_TRY(L.alloc(&off2, (size_t)mm + 1));
-    GB_TRY(L.alloc(&nbr2, (size_t)mm));
+    int32_t *nbr2 = nullptr, *sublabel = nullptr;
+    GB_TRY(arena_alloc(A, (size_t)mm + 1, &flag));
+    GB_TRY(arena_alloc(A, (size_t)mm + 1, &pos));
+    GB_TRY(arena_alloc(A, (size_t)n, &map));
+    GB_TRY(arena_alloc(A, (size_t)mm, &rep));
+    GB_TRY(arena_alloc(A, (size_t)mm + 1, &off2));
+    GB_TRY(arena_alloc(A, (size_t)mm, &nbr2));
     hipLaunchKernelGGL(cc_fill_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, map, n, kNone);
     hipLaunchKernelGGL(cc_first_kernel, dim3(gridn((int64_t)mm + 1)), dim3(kBlock), 0, s, keys, mm,
                        bits, flag);
-    size_t tscan = 0;
-    GB_HIP(rocprim::exclusive_scan(nullptr, tscan, flag, pos, 0u, (size_t)mm + 1,
-                                   rocprim::plus<uint32_t>(), s));
-    char* tmp2 = tmp;
-    if (tscan > tmax) GB_TRY(L.alloc(&tmp2, tscan));
-    GB_HIP(rocprim::exclusive_scan(tmp2, tscan, flag, pos, 0u, (size_t)mm + 1,
+    tsz = tmax;
+    GB_HIP(rocprim::exclusive_scan(tmp, tsz, flag, pos, 0u, (size_t)mm + 1,
                                    rocprim::plus<uint32_t>(), s));
     hipLaunchKernelGGL(cc_index_kernel, dim3(gridn(mm)), dim3(kBlock), 0, s, keys, mm, bits, flag,
                        pos, rep, map, off2);
@@ -778,13 +881,12 @@ static int connect_rec(gbgpu_graph g, double beta, uint64_t seed, uint32_t level
     uint32_t k2 = 0;
     GB_HIP(hipMemcpyAsync(&k2, pos + mm, 4, hipMemcpyDeviceToHost, s));
     GB_HIP(hipStreamSynchronize(s));
-    gbgpu_graph sub = nullptr;
-    GB_TRY(gbgpu_load_csr((int64_t)k2, (int64_t)mm, off2, nbr2, nullptr, GBGPU_SYMMETRIC, s, &sub));
-    int32_t* sublabel = nullptr;
-    int st = L.alloc(&sublabel, (size_t)k2);
-    if (st == GBGPU_OK) st = connect_rec(sub, beta, seed, level + 1, sublabel, o, s, levels_out);
-    (void)gbgpu_graph_free(sub);
-    if (st != GBGPU_OK) return st;
+    GB_TRY(arena_alloc(A, (size_t)k2, &deg2));
+    GB_TRY(arena_alloc(A, (size_t)k2, &sublabel));
+    hipLaunchKernelGGL(cc_deg_kernel, dim3(gridn(k2)), dim3(kBlock), 0, s, off2, (int64_t)k2, deg2);
+    GB_HIP(hipGetLastError());
+    const GView sub{(int64_t)k2, (int64_t)mm, off2, nbr2, deg2};
+    GB_TRY(connect_rec(sub, beta, seed, level + 1, sublabel, o, s, A, levels_out));
     hipLaunchKernelGGL(cc_compose_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, cluster, n,
                        (const uint32_t*)map, (const uint32_t*)rep, sublabel, label);
     GB_HIP(hipGetLastError());
@@ -807,15 +909,21 @@ int gbgpu_ldd(gbgpu_graph g, double beta, uint64_t seed, int32_t* cluster, const
     const gbgpu_opts opt = resolve_opts(o);
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g->mu);
-    LddWs* w = nullptr;
-    GB_TRY(new_ldd_ws(g->n, &w));
-    std::unique_ptr<LddWs, void (*)(LddWs*)> wg(w, free_ldd_ws);
+    Arena* A = nullptr;
+    GB_TRY(arena_begin(g, ldd_ws_bytes(g->n), &A));
+    struct End {
+        Arena* A;
+        ~End() { arena_end(A); }
+    } end{A};
+    LddWs w;
+    GB_TRY(new_ldd_ws(*A, g->n, &w));
+    const GView v{g->n, g->m, g->off, g->nbr, g->deg};
     int32_t rounds = 0;
-    GB_TRY(run_ldd(g, beta, seed, 0, cluster, opt, s, w, &rounds));
+    GB_TRY(run_ldd(v, beta, seed, 0, cluster, opt, s, &w, &rounds));
+    int64_t k = 0;
+    if (st) GB_TRY(count_self(cluster, g->n, w.ctl + 6, s, &k));
     GB_HIP(hipStreamSynchronize(s));
     if (st) {
-        int64_t k = 0;
-        GB_TRY(count_self(cluster, g->n, w->ctl + 6, s, &k));
         memset(st, 0, sizeof(*st));
         st->rounds = rounds;
         st->reached = k;
@@ -833,30 +941,31 @@ int gbgpu_connectivity(gbgpu_graph g, double beta, uint64_t seed, int32_t* label
     const gbgpu_opts opt = resolve_opts(o);
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g->mu);
+    const int64_t n = g->n;
+    Arena* A = nullptr;
+    GB_TRY(arena_begin(g,
+                       ldd_ws_bytes(n) + 4 * b256((size_t)n * 4 + 8) +
+                           b256(8 * (size_t)std::min<int64_t>(g->m, std::max<int64_t>(1 << 20, g->m / 64))),
+                       &A));
+    struct End {
+        Arena* A;
+        ~End() { arena_end(A); }
+    } end{A};
+    const GView v{n, g->m, g->off, g->nbr, g->deg};
     int32_t levels = 0;
-    GB_TRY(connect_rec(g, beta, seed, 0, label, opt, s, &levels));
+    GB_TRY(connect_rec(v, beta, seed, 0, label, opt, s, *A, &levels));
     // canonical labels: the smallest vertex id of each component
     uint32_t* minv = nullptr;
-    if (hipMalloc(&minv, (size_t)g->n * 4 + 16) != hipSuccess)
-        return set_error(GBGPU_E_NOMEM, "connectivity label buffer");
-    hipLaunchKernelGGL(cc_fill_kernel, dim3(gridn(g->n)), dim3(kBlock), 0, s, minv, g->n,
-                       0xFFFFFFFFu);
-    hipLaunchKernelGGL(cc_canon_min_kernel, dim3(gridn(g->n)), dim3(kBlock), 0, s, label, g->n,
-                       minv);
-    hipLaunchKernelGGL(cc_canon_apply_kernel, dim3(gridn(g->n)), dim3(kBlock), 0, s, label, g->n,
-                       minv);
-    const hipError_t e1 = hipGetLastError();
-    const hipError_t e2 = hipStreamSynchronize(s);
-    int rc = GBGPU_OK;
-    if (e1 != hipSuccess || e2 != hipSuccess)
-        rc = set_error(GBGPU_E_HIP, "connectivity labels: %s",
-                       hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    unsigned long long* slot = nullptr;
+    GB_TRY(arena_alloc(*A, (size_t)n, &minv));
+    GB_TRY(arena_alloc(*A, 1, &slot));
+    hipLaunchKernelGGL(cc_fill_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, minv, n, 0xFFFFFFFFu);
+    hipLaunchKernelGGL(cc_canon_min_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, label, n, minv);
+    hipLaunchKernelGGL(cc_canon_apply_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, label, n, minv);
+    GB_HIP(hipGetLastError());
     int64_t comps = 0;
-    if (rc == GBGPU_OK && st)
-        rc = count_self(label, g->n,
-                        (unsigned long long*)(minv + (((size_t)g->n + 1) & ~(size_t)1)), s, &comps);
-    (void)hipFree(minv);
-    if (rc != GBGPU_OK) return rc;
+    if (st) GB_TRY(count_self(label, n, slot, s, &comps));
+    GB_HIP(hipStreamSynchronize(s));
     if (st) {
         memset(st, 0, sizeof(*st));
         st->rounds = levels;

@@ -130,6 +130,21 @@ def test_independent_of_beta_and_seed_and_repeatable(gb):
     G.free()
 
 
+def test_many_distinct_cross_edges(gb):
+    """Small clusters on a 128^3 torus (beta 0.95): 1.3 million distinct
+    inter-cluster edges, more than the first key buffer holds (the cross
+    pass runs again with room for all of them)."""
+    g = gg.torus3d(128)
+    G = gb.Graph.from_csr(g, validate=False, with_weights=False)
+    exp = oracle.components(g)
+    for beta in (0.95, 0.5):
+        assert np.array_equal(gb.ldd(G, beta, 17).cpu().numpy(), oracle.ldd(g, beta, 17))
+        lab, st = gb.connectivity(G, beta, 17, stats=True)
+        assert np.array_equal(lab.cpu().numpy(), exp), f"beta={beta}"
+        assert st["reached"] == int(np.unique(exp).size)
+    G.free()
+
+
 def test_bad_beta(gb):
     g = gg.rmat(8, seed=1)
     G = gb.Graph.from_csr(g)
