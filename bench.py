@@ -138,6 +138,8 @@ def main():
                     help="print per-kernel averages of a rocprofv3 --pmc csv directory and exit")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
+    ap.add_argument("--only", choices=["connectivity"], default="",
+                    help="time only the given section (for profiling) and print its own JSON line")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
@@ -165,6 +167,27 @@ def main():
     G = gb.Graph.from_csr(g, validate=False, with_weights=False)
     deg = g.degrees()
     stream = torch.cuda.current_stream()
+    if args.only == "connectivity":
+        # LDD (beta 0.2) and connectivity on the same graph: warmup, then
+        # --steps timed calls of each
+        res = {"metric": "connectivity_section", "config": {"workload": f"rmat{args.scale}",
+                                                             "beta": 0.2}}
+        for key, fn in (("ldd", gb.ldd), ("connectivity", gb.connectivity)):
+            _, st = fn(G, 0.2, 1, stats=True)
+            for _ in range(args.warmup):
+                fn(G, 0.2, 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn(G, 0.2, 1)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+            res[f"{key}_ms"] = round(ms, 3)
+            res[f"{key}_rounds"] = st["rounds"]
+            res[f"{key}_clusters"] = st["reached"]
+            log(f"{key}: {ms:.3f} ms, {st['rounds']} rounds/levels, {st['reached']} clusters/components")
+        print(json.dumps(res), flush=True)
+        return
     if not args.opts and not args.no_tuned:
         from paper_1805_05208_amd import autotune
         _, _, st0 = gb.bfs(G, srcs[0], stats=True)
