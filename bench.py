@@ -138,7 +138,7 @@ def main():
                     help="print per-kernel averages of a rocprofv3 --pmc csv directory and exit")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
-    ap.add_argument("--only", choices=["connectivity"], default="",
+    ap.add_argument("--only", choices=["connectivity", "compressed"], default="",
                     help="time only the given section (for profiling) and print its own JSON line")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -167,6 +167,35 @@ def main():
     G = gb.Graph.from_csr(g, validate=False, with_weights=False)
     deg = g.degrees()
     stream = torch.cuda.current_stream()
+    if args.only == "compressed":
+        # compressed adjacency: size, then BFS over the compressed lists and
+        # the same rounds over the plain lists, --steps timed passes over
+        # the sources
+        nbytes = gb.compress(G)
+        res = {"metric": "compressed_section", "config": {"workload": f"rmat{args.scale}",
+                                                           "sources": len(srcs)},
+               "compressed_bytes": nbytes,
+               "list_bytes_per_edge": round((nbytes - 8 * (g.n + 1)) / g.m, 3)}
+        edges = 0
+        for s in srcs:
+            d, _ = gb.bfs(G, s)
+            edges += int(deg[d.cpu().numpy() != 2**31 - 1].sum()) // 2
+        for key, fn in (("bfs_compressed", gb.bfs_compressed), ("bfs_simple", gb.bfs_simple)):
+            for _ in range(args.warmup):
+                for s in srcs:
+                    fn(G, s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                for s in srcs:
+                    fn(G, s)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / max(args.steps, 1)
+            res[f"{key}_gteps"] = round(edges / dt / 1e9, 2)
+            res[f"{key}_ms_per_source"] = round(dt * 1e3 / len(srcs), 3)
+            log(f"{key}: {res[f'{key}_ms_per_source']} ms/source, {res[f'{key}_gteps']} GTEPS")
+        print(json.dumps(res), flush=True)
+        return
     if args.only == "connectivity":
         # LDD (beta 0.2) and connectivity on the same graph: warmup, then
         # --steps timed calls of each
@@ -422,6 +451,24 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         extra["bc_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
         extra["bc_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
         log(f"betweenness rmat: {extra['bc_rmat24_ms']} ms/source, {extra['bc_rmat24_gteps']} GTEPS")
+        # compressed adjacency: size, and the same simple rounds over the
+        # compressed and over the plain lists (same sources as the headline)
+        nbytes = gb.compress(G)
+        extra["compressed_rmat24_list_bytes_per_edge"] = round((nbytes - 8 * (g.n + 1)) / g.m, 3)
+        extra["compressed_rmat24_bytes"] = nbytes
+        e4 = 0
+        for s in srcs[:4]:
+            d, _ = gb.bfs(G, s)
+            e4 += int(deg[d.cpu().numpy() != 2**31 - 1].sum()) // 2
+        for key, fn in (("bfs_compressed", gb.bfs_compressed), ("bfs_simple", gb.bfs_simple)):
+            tot_t = 0.0
+            for s in srcs[:4]:
+                tot_t += timed(lambda: fn(G, s), reps=2)
+            extra[f"{key}_rmat24_gteps"] = round(e4 / tot_t / 1e9, 2)
+            extra[f"{key}_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
+            log(f"{key} rmat: {extra[f'{key}_rmat24_ms']} ms/source, {extra[f'{key}_rmat24_gteps']} GTEPS")
+        log(f"compressed lists: {extra['compressed_rmat24_list_bytes_per_edge']} B/edge "
+            f"(plain 4), {nbytes / 1e9:.2f} GB with offsets")
         # low-diameter decomposition and connectivity (beta 0.2): whole graph
         for key, fn in (("ldd", gb.ldd), ("connectivity", gb.connectivity)):
             _, st = fn(G, 0.2, 1, stats=True)

@@ -221,6 +221,37 @@ int gbgpu_widest_path(gbgpu_graph g, int32_t src, uint32_t* width, const gbgpu_o
 int gbgpu_bc(gbgpu_graph g, int32_t src, double* dep, const gbgpu_opts* o, gbgpu_stats* st,
              void* stream);
 
+/* Compressed adjacency (the paper's "Compression" section: blocked,
+ * independently decodable neighbour lists).  Builds a compressed copy of the
+ * graph's lists, owned by the handle (replacing an earlier one): each sorted
+ * list is cut into blocks of 64 neighbours; a block stores its first
+ * neighbour, a bit width w (bit length of last - first) and each
+ * neighbour's offset from the first in w bits; lists of more than one block
+ * start with a table of block offsets.  Word offsets per vertex are int64.
+ *   bytes   optional host output: size of the copy (lists + offsets)
+ * Errors: E_INVALID for a null handle; E_NOMEM.  Synchronous. */
+int gbgpu_compress(gbgpu_graph g, int64_t* bytes, void* stream);
+
+/* Decodes the compressed copy into neighbors (dev int32[m], the CSR order);
+ * equal to the graph's own neighbour array.  E_INVALID without a copy. */
+int gbgpu_decompress(gbgpu_graph g, int32_t* neighbors, void* stream);
+
+/* BFS that reads only the compressed lists and the degrees (BFS algorithm
+ * box; rounds of push with a min-ID atomic claim or pull taking the first
+ * frontier neighbour in list order, chosen on the device from the
+ * frontier's vertex and degree totals with tau, forced by force_direction).
+ * Outputs and encodings as gbgpu_bfs (identical results).
+ * Errors: as gbgpu_bfs; E_INVALID when the graph has no compressed copy. */
+int gbgpu_bfs_compressed(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+                         const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
+/* The same rounds and kernels as gbgpu_bfs_compressed over the plain
+ * neighbour array: the baseline that isolates the effect of compression
+ * (gbgpu_bfs is the faster general BFS).  Same outputs and errors, without
+ * the compressed-copy requirement. */
+int gbgpu_bfs_simple(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+                     const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
 /* Low-diameter decomposition (the paper's LDD algorithm box after Miller,
  * Peng and Xu, "Connectivity Problems" section).  Vertex v draws a shift
  * g(v); with start(v) = max g - g(v), round r first makes every unvisited

@@ -28,6 +28,7 @@ EXPORTED = [
     "gbgpu_last_error", "gbgpu_version", "gbgpu_load_csr", "gbgpu_graph_free",
     "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bellman_ford", "gbgpu_widest_path",
     "gbgpu_bc", "gbgpu_ldd", "gbgpu_connectivity",
+    "gbgpu_compress", "gbgpu_decompress", "gbgpu_bfs_compressed", "gbgpu_bfs_simple",
     "gbgpu_bfs_multi", "gbgpu_bfs_batch",
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
@@ -104,6 +105,10 @@ def lib() -> ctypes.CDLL:
             "gbgpu_widest_path": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_bc": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_ldd": ([P, ctypes.c_double, ctypes.c_uint64, P, P, P, P], ctypes.c_int),
+            "gbgpu_compress": ([P, P, P], ctypes.c_int),
+            "gbgpu_decompress": ([P, P, P], ctypes.c_int),
+            "gbgpu_bfs_compressed": ([P, I32, P, P, P, P, P], ctypes.c_int),
+            "gbgpu_bfs_simple": ([P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_connectivity": ([P, ctypes.c_double, ctypes.c_uint64, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_multi": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_batch": ([P, P, I32, P, P, P, P, P], ctypes.c_int),
@@ -440,3 +445,40 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def compress(g: Graph, stream=None) -> int:
+    """Builds the graph's compressed copy of its lists; returns its size in
+    bytes (lists + per-vertex offsets)."""
+    b = ctypes.c_int64(0)
+    _check(lib().gbgpu_compress(g.handle, ctypes.byref(b), _stream_ptr(stream)))
+    return int(b.value)
+
+
+def decompress(g: Graph, out=None, stream=None):
+    """Neighbour array decoded from the compressed copy (int32[m])."""
+    out = _out(out, max(g.m, 1), torch.int32)
+    _check(lib().gbgpu_decompress(g.handle, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out[: g.m]
+
+
+def _bfs_lists(fn, g, src, dist, parent, opts, stream, stats):
+    dist = _out(dist, g.n, torch.int32)
+    parent = _out(parent, g.n, torch.int32)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(fn(g.handle, int(src), ctypes.c_void_p(dist.data_ptr()),
+              ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats), _stream_ptr(stream)))
+    return (dist, parent, st.as_dict()) if stats else (dist, parent)
+
+
+def bfs_compressed(g: Graph, src: int, dist=None, parent=None, opts=None, stream=None,
+                   stats: bool = False):
+    """BFS reading only the compressed lists (call compress first)."""
+    return _bfs_lists(lib().gbgpu_bfs_compressed, g, src, dist, parent, opts, stream, stats)
+
+
+def bfs_simple(g: Graph, src: int, dist=None, parent=None, opts=None, stream=None,
+               stats: bool = False):
+    """The same rounds as bfs_compressed over the plain lists."""
+    return _bfs_lists(lib().gbgpu_bfs_simple, g, src, dist, parent, opts, stream, stats)

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgbgpu.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["graph.hip", "bfs.hip", "wbfs.hip", "multi.hip", "server.hip", "sr.hip", "bc.hip", "ldd.hip"]
+SOURCES = ["graph.hip", "bfs.hip", "wbfs.hip", "multi.hip", "server.hip", "sr.hip", "bc.hip", "ldd.hip", "cadj.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

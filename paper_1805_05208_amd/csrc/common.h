@@ -52,6 +52,8 @@ struct BcWs;
 void free_bc_ws(BcWs* w);
 struct Arena;
 void free_arena(Arena* a);
+struct CAdj;
+void free_cadj(CAdj* c);
 // Workspace of multi-source BFS (multi.hip).
 struct MultiWs;
 
@@ -89,6 +91,7 @@ struct gbgpu_graph_s {
     gb::BfsWs* sr = nullptr;     // workspace of the Bellman-Ford / widest-path rounds
     gb::BcWs* bc = nullptr;      // workspace of betweenness centrality
     gb::Arena* cc = nullptr;     // device arena of the LDD / connectivity calls
+    gb::CAdj* cadj = nullptr;    // compressed copy of the lists and its BFS workspace
     gb::WbfsWs* wbfs = nullptr;
     gb::MultiWs* multi = nullptr;
 };

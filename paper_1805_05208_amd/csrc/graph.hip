@@ -495,6 +495,7 @@ int gbgpu_graph_free(gbgpu_graph g) {
         free_bfs_ws(g->sr);
         free_bc_ws(g->bc);
         free_arena(g->cc);
+        free_cadj(g->cadj);
         free_wbfs_ws(g->wbfs);
         free_multi_ws(g->multi);
         if (g->plan) (void)hipFree(g->plan);

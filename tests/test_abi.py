@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     for required in ["gbgpu_load_csr", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_submit", "gbgpu_poll",
                      "gbgpu_bfs_multi", "gbgpu_bfs_batch", "gbgpu_last_error",
                      "gbgpu_bellman_ford", "gbgpu_widest_path", "gbgpu_bc",
-                     "gbgpu_ldd", "gbgpu_connectivity"]:
+                     "gbgpu_ldd", "gbgpu_connectivity", "gbgpu_compress", "gbgpu_decompress",
+                     "gbgpu_bfs_compressed", "gbgpu_bfs_simple"]:
         assert required in names
 
 

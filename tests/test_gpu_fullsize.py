@@ -14,7 +14,10 @@
 * single-source betweenness from the first timed source, RMAT-24 and torus,
   against the oracle within the tolerance of test_gpu_bc.py;
 * low-diameter decomposition (beta 0.2, the seed the benchmark uses) and
-  connectivity, RMAT-24 and torus, element by element against the oracle.
+  connectivity, RMAT-24 and torus, element by element against the oracle;
+* compressed adjacency: RMAT-24 decoded back exactly, and BFS over the
+  compressed lists from the first two timed sources against the oracle;
+  torus 256^3 against the closed form.
 """
 import json
 import os
@@ -174,3 +177,24 @@ def test_ldd_and_connectivity(gb, which, request):
     assert bad.size == 0, f"{which} connectivity: {bad.size} differ, first v={bad[0]}"
     if own:
         G.free()
+
+
+def test_rmat24_compressed(gb, rmat24):
+    g, _, G = rmat24
+    gb.compress(G)
+    assert np.array_equal(gb.decompress(G).cpu().numpy(), g.nbrs)
+    for s in [int(x) for x in gg.sources(g, 16, seed=3)[:2]]:
+        d, p = gb.bfs_compressed(G, s)
+        od, op = oracle.bfs(g, s)
+        assert_same(d.cpu().numpy(), p.cpu().numpy(), od, op, f"rmat24 compressed src={s}")
+
+
+def test_torus256_compressed(gb):
+    g = gg.torus3d(256)
+    G = gb.Graph.from_csr(g, validate=False, with_weights=False)
+    gb.compress(G)
+    s = int(gg.sources(g, 1, seed=3)[0])
+    d, p = gb.bfs_compressed(G, s)
+    ed, ep = torus_closed_form(256, s)
+    assert_same(d.cpu().numpy(), p.cpu().numpy(), ed, ep, "torus256 compressed")
+    G.free()
