@@ -268,9 +268,11 @@ int gbgpu_bfs_simple(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
  *   cluster dev int32[n] output: the centre vertex of v's cluster
  *   o, st   optional (NULL allowed); st->rounds = rounds run, st->reached =
  *           number of clusters
- * Weights, when present, are ignored.  Errors: E_INVALID for a null
- * handle/output or beta outside (0, 1).  The call returns when cluster is
- * complete. */
+ * Weights, when present, are ignored.  The handle keeps a device arena of
+ * the largest LDD / connectivity call made on it (for RMAT scale 24 about
+ * 1 GB) until gbgpu_graph_free.  Errors: E_INVALID for a null
+ * handle/output or beta outside (0, 1); E_NOMEM.  The call returns when
+ * cluster is complete. */
 int gbgpu_ldd(gbgpu_graph g, double beta, uint64_t seed, int32_t* cluster,
               const gbgpu_opts* o, gbgpu_stats* st, void* stream);
 

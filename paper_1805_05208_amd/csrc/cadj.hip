@@ -614,8 +614,11 @@ static int bfs_lists(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
         return set_error(GBGPU_E_INVALID, "graph has no compressed lists (call gbgpu_compress)");
     if (!g->cadj) g->cadj = new CAdj();
     hipStream_t s = (hipStream_t)stream;
-    return comp ? run_cbfs<true>(g, src, dist, parent, opt, st, s)
-                : run_cbfs<false>(g, src, dist, parent, opt, st, s);
+    const int rc = comp ? run_cbfs<true>(g, src, dist, parent, opt, st, s)
+                        : run_cbfs<false>(g, src, dist, parent, opt, st, s);
+    // an early error may leave rounds queued that use the workspace
+    if (rc != GBGPU_OK) (void)hipStreamSynchronize(s);
+    return rc;
 }
 
 int gbgpu_bfs_compressed(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,

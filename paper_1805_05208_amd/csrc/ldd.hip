@@ -911,10 +911,16 @@ int gbgpu_ldd(gbgpu_graph g, double beta, uint64_t seed, int32_t* cluster, const
     std::lock_guard<std::mutex> lk(g->mu);
     Arena* A = nullptr;
     GB_TRY(arena_begin(g, ldd_ws_bytes(g->n), &A));
+    // on every return: the stream drained (an early error may leave kernels
+    // queued that use the arena), then the overflow allocations freed
     struct End {
         Arena* A;
-        ~End() { arena_end(A); }
-    } end{A};
+        hipStream_t s;
+        ~End() {
+            (void)hipStreamSynchronize(s);
+            arena_end(A);
+        }
+    } end{A, s};
     LddWs w;
     GB_TRY(new_ldd_ws(*A, g->n, &w));
     const GView v{g->n, g->m, g->off, g->nbr, g->deg};
@@ -949,8 +955,12 @@ int gbgpu_connectivity(gbgpu_graph g, double beta, uint64_t seed, int32_t* label
                        &A));
     struct End {
         Arena* A;
-        ~End() { arena_end(A); }
-    } end{A};
+        hipStream_t s;
+        ~End() {
+            (void)hipStreamSynchronize(s);
+            arena_end(A);
+        }
+    } end{A, s};
     const GView v{n, g->m, g->off, g->nbr, g->deg};
     int32_t levels = 0;
     GB_TRY(connect_rec(v, beta, seed, 0, label, opt, s, *A, &levels));
