@@ -145,8 +145,8 @@ def main():
         pmc_summary(args.pmc_summary)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding a query over several GPUs is a design, not code that runs.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
     GBGPU_OK = 0,
     GBGPU_E_INVALID = 1,     /* bad argument or malformed graph            */
-    GBGPU_E_UNSUPPORTED = 2, /* valid input outside this build's limits    */
+    GBGPU_E_UNSUPPORTED = 2, /* valid input outside the library's limits   */
     GBGPU_E_NOMEM = 3,       /* device or host allocation failed / budget  */
     GBGPU_E_HIP = 4,         /* HIP runtime error                          */
     GBGPU_E_OVERFLOW = 5,    /* distances could exceed 0xFFFFFFFF - 1      */
