@@ -156,6 +156,22 @@ int gbgpu_graph_info(gbgpu_graph g, int64_t* n, int64_t* m, int32_t* max_weight)
 int gbgpu_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
               const gbgpu_opts* o, gbgpu_stats* st, void* stream);
 
+/* k single-source BFS one after another on one stream (same algorithm and
+ * results as k calls of gbgpu_bfs): each search starts as soon as the device
+ * reports the previous one's empty frontier, with no return to the caller in
+ * between.
+ *   srcs        host int32[k], each in [0, n) (repeats allowed)
+ *   dist/parent dev int32 outputs; search i writes dist + i * row_stride and
+ *               parent + i * row_stride (row_stride = 0: every search writes
+ *               the same n entries, so they end holding the last search's)
+ *   row_stride  0 or >= n
+ *   st          optional: rounds, launches, reached, edges summed over the
+ *               k searches; wall_ms of the whole call
+ * Errors: E_INVALID for k < 1, a bad source or stride, null pointers. */
+int gbgpu_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist,
+                   int32_t* parent, int64_t row_stride, const gbgpu_opts* o,
+                   gbgpu_stats* st, void* stream);
+
 /* Single-source integral-weight SSSP (weighted BFS problem statement; the
  * paper's wBFS algorithm box: buckets by distance, edgeMapData relaxations
  * with priority-write).

@@ -29,6 +29,7 @@ EXPORTED = [
     "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bellman_ford", "gbgpu_widest_path",
     "gbgpu_bc", "gbgpu_ldd", "gbgpu_connectivity",
     "gbgpu_compress", "gbgpu_decompress", "gbgpu_bfs_compressed", "gbgpu_bfs_simple",
+    "gbgpu_bfs_many",
     "gbgpu_bfs_multi", "gbgpu_bfs_batch",
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
             "gbgpu_graph_free": ([P], ctypes.c_int),
             "gbgpu_graph_info": ([P, P, P, P], ctypes.c_int),
             "gbgpu_bfs": ([P, I32, P, P, P, P, P], ctypes.c_int),
+            "gbgpu_bfs_many": ([P, P, I32, P, P, I64, P, P, P], ctypes.c_int),
             "gbgpu_wbfs": ([P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bellman_ford": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_widest_path": ([P, I32, P, P, P, P], ctypes.c_int),
@@ -262,6 +264,29 @@ def bfs(g: Graph, src: int, dist=None, parent=None, opts=None, stream=None,
     _check(lib().gbgpu_bfs(g.handle, int(src), ctypes.c_void_p(dist.data_ptr()),
                            ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats),
                            _stream_ptr(stream)))
+    return (dist, parent, st.as_dict()) if stats else (dist, parent)
+
+
+def bfs_many(g: Graph, srcs, dist=None, parent=None, row_stride=None, opts=None, stream=None,
+             stats: bool = False):
+    """k single-source BFS back to back inside the library.  Without outputs
+    given, returns (dist, parent) of shape [k, n]; row_stride 0 makes every
+    search write the same n entries."""
+    src = np.ascontiguousarray(np.asarray(srcs, dtype=np.int32))
+    k = int(src.size)
+    if row_stride is None:
+        row_stride = g.n
+    rows = k if row_stride else 1
+    need = (rows - 1) * row_stride + g.n if rows > 1 else g.n
+    dist = _out(dist, need, torch.int32)
+    parent = _out(parent, need, torch.int32)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(lib().gbgpu_bfs_many(g.handle, src.ctypes.data_as(ctypes.c_void_p), k,
+                                ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(parent.data_ptr()),
+                                int(row_stride), oref, _st_ref(st, stats), _stream_ptr(stream)))
+    if row_stride == g.n and dist.numel() == k * g.n:
+        dist, parent = dist.view(k, g.n), parent.view(k, g.n)
     return (dist, parent, st.as_dict()) if stats else (dist, parent)
 
 

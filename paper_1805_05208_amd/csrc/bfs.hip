@@ -713,9 +713,12 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
 // be pending unless sync_end is set.  They only touch the workspace, and the
 // next run on it (on any stream) waits for them.
 int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* parent,
-               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool sync_end) {
+               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool sync_end,
+               bool wait_prev) {
     const double t0 = now_ms();
-    GB_HIP(hipStreamWaitEvent(stream, w->done, 0));
+    // the workspace's last user may have been another stream (not needed when
+    // the previous search ran on this same stream)
+    if (wait_prev) GB_HIP(hipStreamWaitEvent(stream, w->done, 0));
     BfsArgs a;
     a.off = g->off;
     a.nbr = g->nbr;
@@ -810,7 +813,38 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
 int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
             gbgpu_stats* st, hipStream_t stream) {
     GB_TRY(ensure_bfs_ws(g));
-    return run_bfs_ws(g, g->bfs, src, dist, parent, o, st, stream, false);
+    return run_bfs_ws(g, g->bfs, src, dist, parent, o, st, stream, false, true);
+}
+
+// k searches one after another on one stream: the next starts as soon as
+// the device reports the previous one's empty frontier, without a return
+// to the caller in between.
+int run_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist, int32_t* parent,
+                 int64_t stride, const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream) {
+    GB_TRY(ensure_bfs_ws(g));
+    const double t0 = now_ms();
+    gbgpu_stats sum;
+    memset(&sum, 0, sizeof(sum));
+    for (int32_t i = 0; i < k; ++i) {
+        gbgpu_stats one;
+        GB_TRY(run_bfs_ws(g, g->bfs, srcs[i], dist + (int64_t)i * stride,
+                          parent + (int64_t)i * stride, o, st ? &one : nullptr, stream, false,
+                          i == 0));
+        if (st) {
+            sum.rounds += one.rounds;
+            sum.push_rounds += one.push_rounds;
+            sum.pull_rounds += one.pull_rounds;
+            sum.launches += one.launches;
+            sum.reached += one.reached;
+            sum.edges_examined += one.edges_examined;
+            sum.kernel_ms += one.kernel_ms;
+        }
+    }
+    if (st) {
+        sum.wall_ms = now_ms() - t0;
+        *st = sum;
+    }
+    return GBGPU_OK;
 }
 
 // Round log of the last BFS on this graph: 4 words per round (direction 1 =

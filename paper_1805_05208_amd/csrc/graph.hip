@@ -135,6 +135,8 @@ gbgpu_opts resolve_opts(const gbgpu_opts* o) {
 
 int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
             gbgpu_stats* st, hipStream_t stream);
+int run_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist, int32_t* parent,
+                 int64_t stride, const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream);
 int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts& o,
              gbgpu_stats* st, hipStream_t stream);
 int bfs_round_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds);
@@ -527,6 +529,23 @@ int gbgpu_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const 
     gbgpu_opts opt = resolve_opts(o);
     std::lock_guard<std::mutex> lk(g->mu);
     return run_bfs(g, src, dist, parent, opt, st, (hipStream_t)stream);
+}
+
+int gbgpu_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist,
+                   int32_t* parent, int64_t row_stride, const gbgpu_opts* o, gbgpu_stats* st,
+                   void* stream) {
+    if (!g) return set_error(GBGPU_E_INVALID, "graph is NULL");
+    if (!srcs || k < 1) return set_error(GBGPU_E_INVALID, "need k >= 1 sources");
+    if (!dist || !parent) return set_error(GBGPU_E_INVALID, "dist/parent is NULL");
+    if (row_stride != 0 && row_stride < g->n)
+        return set_error(GBGPU_E_INVALID, "row_stride must be 0 or at least n");
+    for (int32_t i = 0; i < k; ++i)
+        if (srcs[i] < 0 || srcs[i] >= g->n)
+            return set_error(GBGPU_E_INVALID, "srcs[%d] = %d out of range [0, %lld)", i, srcs[i],
+                             (long long)g->n);
+    gbgpu_opts opt = resolve_opts(o);
+    std::lock_guard<std::mutex> lk(g->mu);
+    return run_bfs_many(g, srcs, k, dist, parent, row_stride, opt, st, (hipStream_t)stream);
 }
 
 int gbgpu_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts* o,

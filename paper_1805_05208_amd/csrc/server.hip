@@ -28,7 +28,8 @@ void bfs_ws_attach(BfsWs* w, void* mem, int64_t n, int64_t nwords);
 int bfs_ws_host_init(BfsWs* w);
 BfsWs* bfs_ws_new();
 int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* parent,
-               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool sync_end);
+               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool sync_end,
+               bool wait_prev);
 uint32_t wbfs_window(int32_t maxw, int32_t req);
 uint32_t wbfs_default_capacity(int64_t n);
 size_t wbfs_bytes(int64_t n, uint32_t NB, uint32_t C);
@@ -216,7 +217,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
             bfs_ws_attach(w->bws, mem, g->n, g->nwords);
             gbgpu_stats st;
             status = run_bfs_ws(g, w->bws, job[0].q.src, (int32_t*)job[0].q.dist, job[0].q.parent,
-                                sv->opts, &st, w->stream, true);  // the arena is reused at once
+                                sv->opts, &st, w->stream, true, true);  // the arena is reused at once
             rounds = st.rounds;
         } else {
             const uint32_t NB = wbfs_window(g->maxw, sv->opts.bucket_window);

@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
                      "gbgpu_bfs_multi", "gbgpu_bfs_batch", "gbgpu_last_error",
                      "gbgpu_bellman_ford", "gbgpu_widest_path", "gbgpu_bc",
                      "gbgpu_ldd", "gbgpu_connectivity", "gbgpu_compress", "gbgpu_decompress",
-                     "gbgpu_bfs_compressed", "gbgpu_bfs_simple"]:
+                     "gbgpu_bfs_compressed", "gbgpu_bfs_simple", "gbgpu_bfs_many"]:
         assert required in names
 
 
