@@ -250,8 +250,7 @@ struct LddArgs {
 // stays out of the queue (the late rounds inject every isolated vertex).
 // Queue entries go through the workgroup's LDS buffer: one reservation per
 // workgroup rather than one per wavefront.
-__global__ __launch_bounds__(kRBlock, 8) void ldd_inject_kernel(LddArgs a) {
-    __shared__ WgQueue q;
+__device__ __forceinline__ void ldd_inject_body(const LddArgs& a, WgQueue& q) {
     wgq_init(q);
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -296,6 +295,11 @@ __global__ __launch_bounds__(kRBlock, 8) void ldd_inject_kernel(LddArgs a) {
     wgq_finish(q, out, true);
 }
 
+__global__ __launch_bounds__(kRBlock, 8) void ldd_inject_kernel(LddArgs a) {
+    __shared__ WgQueue q;
+    ldd_inject_body(a, q);
+}
+
 // Round r, part 2, sparse: the frontier queue claims its unvisited
 // neighbours with a 64-bit atomic minimum of (claimer id, cluster); the
 // smallest claimer id wins.  Visited bits are not touched during the round,
@@ -338,8 +342,8 @@ struct LddPushPolicy {
 // smallest claimer id, so the same result without atomics; a lane scans
 // `light` neighbours, then its wavefront scans the rest 64 at a time.  Both
 // emit the claimed vertices as the next queue and bitmap.
-__global__ __launch_bounds__(kRBlock, 8) void ldd_round_kernel(LddArgs a, uint32_t chunk_cap) {
-    __shared__ WgQueue q;
+__device__ __forceinline__ void ldd_round_body(const LddArgs& a, uint32_t chunk_cap,
+                                               WgQueue& q) {
     wgq_init(q);
     __syncthreads();
     const unsigned long long packed = *(volatile unsigned long long*)a.qcnt_c;
@@ -427,6 +431,56 @@ __global__ __launch_bounds__(kRBlock, 8) void ldd_round_kernel(LddArgs a, uint32
     wgq_finish(q, out, true);
 }
 
+__global__ __launch_bounds__(kRBlock, 8) void ldd_round_kernel(LddArgs a, uint32_t chunk_cap) {
+    __shared__ WgQueue q;
+    ldd_round_body(a, chunk_cap, q);
+}
+
+// Per-round arguments from the workspace (the pointers alternate by round).
+__device__ __forceinline__ void ldd_round_args(LddArgs& a, uint32_t r, uint32_t* const F[2],
+                                                        uint32_t* const Q[2], uint32_t* const P[2],
+                                                        unsigned long long* ctl) {
+    a.Fc = F[r & 1];
+    a.Fn = F[(r + 1) & 1];
+    a.Qc = Q[r & 1];
+    a.Pc = P[r & 1];
+    a.Qn = Q[(r + 1) & 1];
+    a.Pn = P[(r + 1) & 1];
+    a.qcnt_c = ctl + (r & 1);
+    a.qcnt_n = ctl + ((r + 1) & 1);
+    a.qover_c = ctl + 2 + (r & 1);
+    a.qover_n = ctl + 2 + ((r + 1) & 1);
+    a.tot = ctl + 128;
+    a.b0 = (uint32_t)ctl[8 + r];
+    a.b1 = (uint32_t)ctl[8 + r + 1];
+}
+
+struct LddSmall {
+    LddArgs a;  // the round-invariant fields
+    uint32_t* F[2];
+    uint32_t* Q[2];
+    uint32_t* P[2];
+    unsigned long long* ctl;
+};
+
+// The whole decomposition of a small graph in one workgroup: the same
+// injection and round steps, separated by workgroup barriers instead of
+// launches, with the number of rounds and the start buckets read on the
+// device (no host round trip).  Every loop is bounded: max g + 1 <= 64
+// rounds.
+__global__ __launch_bounds__(kRBlock, 1) void ldd_small_kernel(LddSmall S, uint32_t chunk_cap) {
+    __shared__ WgQueue q;
+    const uint32_t gmax = (uint32_t)S.ctl[4];
+    for (uint32_t r = 0; r <= gmax; ++r) {
+        LddArgs a = S.a;
+        ldd_round_args(a, r, S.F, S.Q, S.P, S.ctl);
+        ldd_inject_body(a, q);
+        __syncthreads();
+        if (r < gmax) ldd_round_body(a, chunk_cap, q);
+        __syncthreads();
+    }
+}
+
 // Number of v with x[v] == v (cluster centres; canonical component
 // labels): one atomic per workgroup.
 __global__ __launch_bounds__(kBlock) void count_self_kernel(const int32_t* x, int64_t n,
@@ -470,6 +524,11 @@ static int gridn(int64_t items) {
     return (int)std::max<int64_t>(1, std::min<int64_t>((items + kBlock - 1) / kBlock, 4096));
 }
 
+// Graphs up to this size run the whole decomposition in one workgroup
+// (ldd_small_kernel): at most 64 vertices of work per thread and round.
+constexpr int64_t kSmallN = 1 << 16;
+constexpr int64_t kSmallM = 1 << 20;
+
 // One LDD of g into cluster[] (centre ids).  Returns the rounds run.
 static int run_ldd(const GView& g, double beta, uint64_t seed, uint32_t level, int32_t* cluster,
                    const gbgpu_opts& o, hipStream_t s, LddWs* w, int32_t* rounds_out) {
@@ -486,6 +545,38 @@ static int run_ldd(const GView& g, double beta, uint64_t seed, uint32_t level, i
     hipLaunchKernelGGL(ldd_bucket_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, w->keys_sorted, n,
                        w->ctl);
     GB_HIP(hipGetLastError());
+    if (o.force_direction == 0 && n <= kSmallN && g.m <= kSmallM) {
+        // small graph: every round in one workgroup, one launch
+        LddSmall S;
+        S.a.off = g.off;
+        S.a.nbr = g.nbr;
+        S.a.deg = g.deg;
+        S.a.key = w->key;
+        S.a.vis = w->vis;
+        S.a.byst = w->byst;
+        S.a.nwords = (uint32_t)nwords;
+        S.a.n = (uint32_t)n;
+        S.a.dense_at = (uint64_t)(g.m / std::max(1, o.tau));
+        S.a.light = (uint32_t)o.pull_light;
+        for (int i = 0; i < 2; ++i) {
+            S.F[i] = w->F[i];
+            S.Q[i] = w->Q[i];
+            S.P[i] = w->P[i];
+        }
+        S.ctl = w->ctl;
+        hipLaunchKernelGGL(ldd_small_kernel, dim3(1), dim3(kRBlock), 0, s, S,
+                           (uint32_t)o.wave_chunk);
+        hipLaunchKernelGGL(ldd_label_kernel, dim3(gridn(n)), dim3(kBlock), 0, s, w->key, n,
+                           cluster);
+        GB_HIP(hipGetLastError());
+        if (rounds_out) {
+            unsigned long long gm = 0;
+            GB_HIP(hipMemcpyAsync(&gm, w->ctl + 4, 8, hipMemcpyDeviceToHost, s));
+            GB_HIP(hipStreamSynchronize(s));
+            *rounds_out = (int32_t)gm + 1;
+        }
+        return GBGPU_OK;
+    }
     unsigned long long hc[8 + 65];
     GB_HIP(hipMemcpyAsync(hc, w->ctl, sizeof(hc), hipMemcpyDeviceToHost, s));
     GB_HIP(hipStreamSynchronize(s));
