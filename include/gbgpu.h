@@ -1,7 +1,10 @@
 /*
  * gbgpu -- frontier traversal (edgeMap) over a resident CSR graph on one
  * MI355X (gfx950) GPU: breadth-first search and integral-weight SSSP
- * (weighted BFS), single-source, multi-source batched, and served.
+ * (weighted BFS), single-source, multi-source batched, and served; and on
+ * the same rounds general-weight SSSP (Bellman-Ford), widest path,
+ * single-source betweenness, low-diameter decomposition, connectivity, and
+ * BFS over compressed neighbour lists.
  *
  * Operations follow the problem statements of the paper's Benchmark section,
  * "Shortest Path Problems" (Dhulipala, Blelloch, Shun, "Theoretically
