@@ -138,7 +138,8 @@ def main():
                     help="print per-kernel averages of a rocprofv3 --pmc csv directory and exit")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
-    ap.add_argument("--only", choices=["connectivity", "compressed"], default="",
+    ap.add_argument("--only", choices=["connectivity", "compressed", "wbfs", "sssp", "bc"],
+                    default="",
                     help="time only the given section (for profiling) and print its own JSON line")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -167,6 +168,42 @@ def main():
     G = gb.Graph.from_csr(g, validate=False, with_weights=False)
     deg = g.degrees()
     stream = torch.cuda.current_stream()
+    if args.only in ("wbfs", "sssp", "bc"):
+        # one section on the same graph and the first four sources: weighted
+        # BFS, Bellman-Ford and widest path (weights in [1, 24)), or
+        # betweenness; --warmup untimed then --steps timed passes
+        srcs4 = srcs[:4]
+        if args.only == "bc":
+            runs = [("betweenness", lambda s: gb.betweenness(G, s), G)]
+        else:
+            Gw = gb.Graph(G.offsets, G.nbrs, gg.weights(g, 24, seed=2), validate=False)
+            if args.only == "wbfs":
+                runs = [("wbfs", lambda s: gb.wbfs(Gw, s), Gw)]
+            else:
+                runs = [("bellman_ford", lambda s: gb.bellman_ford(Gw, s), Gw),
+                        ("widest_path", lambda s: gb.widest_path(Gw, s), Gw)]
+        res = {"metric": f"{args.only}_section", "config": {"workload": f"rmat{args.scale}",
+                                                             "sources": len(srcs4)}}
+        edges = 0
+        for s in srcs4:
+            d, _ = gb.bfs(G, s)
+            edges += int(deg[d.cpu().numpy() != 2**31 - 1].sum()) // 2
+        for key, fn, _gr in runs:
+            for _ in range(args.warmup):
+                for s in srcs4:
+                    fn(s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                for s in srcs4:
+                    fn(s)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / max(args.steps, 1)
+            res[f"{key}_ms_per_source"] = round(dt * 1e3 / len(srcs4), 3)
+            res[f"{key}_gteps"] = round(edges / dt / 1e9, 2)
+            log(f"{key}: {res[f'{key}_ms_per_source']} ms/source, {res[f'{key}_gteps']} GTEPS")
+        print(json.dumps(res), flush=True)
+        return
     if args.only == "compressed":
         # compressed adjacency: size, then BFS over the compressed lists and
         # the same rounds over the plain lists, --steps timed passes over
