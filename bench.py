@@ -613,15 +613,22 @@ def run_uneven_batch(gg, gb):
 
 def run_serving(g, G, gg, gb, torch, nq=400):
     """Poisson arrivals of mixed BFS/wBFS queries on resident graphs."""
-    graphs = [(g, G)]
-    g18 = gg.rmat(18, seed=1).with_weights(18, seed=2)
-    graphs.append((g18, gb.Graph.from_csr(g18, validate=False)))
-    tg = gg.torus3d(128).with_weights(21, seed=2)
-    graphs.append((tg, gb.Graph.from_csr(tg, validate=False)))
+    # six resident graphs, weights uniform in [1, log2 n): RMAT scales 18,
+    # 22, 24 and 26, the 256^3 torus, Erdos-Renyi 2^23 vertices of average
+    # degree 32
     w24 = gg.weights(g, 24, seed=2)
-    Gw = gb.Graph(G.offsets, G.nbrs, w24, validate=False)
-    graphs[0] = (g, Gw)
-    sv = gb.Server(arena_bytes=24 << 30, max_inflight=8)
+    graphs = [(g, gb.Graph(G.offsets, G.nbrs, w24, validate=False))]
+    for name, make, W in (("rmat18", lambda: gg.rmat(18, seed=1), 18),
+                          ("rmat22", lambda: gg.rmat(22, seed=1), 22),
+                          ("rmat26", lambda: gg.rmat(26, seed=1), 26),
+                          ("torus256", lambda: gg.torus3d(256), 24),
+                          ("er23", lambda: gg.erdos_renyi(1 << 23, 32, seed=1), 23)):
+        t = time.perf_counter()
+        h = make().with_weights(W, seed=2)
+        graphs.append((h, gb.Graph.from_csr(h, validate=False)))
+        log(f"serving graph {name}: n={h.n} m={h.m} loaded in {time.perf_counter() - t:.1f}s")
+    # a weighted BFS on RMAT-26 takes ~9 GB of workspace (64 buckets of n/4)
+    sv = gb.Server(arena_bytes=96 << 30, max_inflight=8)
     ids = [sv.add_graph(GG) for _, GG in graphs]
     rng = np.random.default_rng(7)
     srcsets = [gg.sources(h, 32, seed=3) for h, _ in graphs]
@@ -681,7 +688,7 @@ def run_serving(g, G, gg, gb, torch, nq=400):
            "serving_lambda_qps": round(lam, 1),
            "serving_qps": round(nq / el, 1), "serving_p50_ms": round(float(np.percentile(lat, 50)), 3),
            "serving_p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "serving_graphs": "rmat24 (w<24), rmat18 (w<18), torus128 (w<21); 50/50 BFS/wBFS"}
+           "serving_graphs": "rmat18/22/24/26, torus256, er2^23 d32 (w < log2 n); 50/50 BFS/wBFS"}
     log(f"serving: {res}")
     return res
 

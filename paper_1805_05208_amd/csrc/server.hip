@@ -3,8 +3,9 @@
 //
 // Workers (one HIP stream each, default priority) take work from a FIFO of
 // pending queries.  A worker that becomes free takes the oldest query; for a
-// BFS it also takes every other pending BFS on the same graph (up to 64) and
-// runs them together as one bit-packed multi-source traversal.  Work is
+// BFS on a graph known to be shallow and of at most 2^24 vertices it also
+// takes every other pending BFS on the same graph (up to 64) and runs them
+// together as one bit-packed multi-source traversal.  Work is
 // admitted only when its device footprint fits in the arena's free space, so
 // the server never allocates device memory of its own; queries that arrive
 // while others run are picked up as soon as a worker and memory are free, and
@@ -101,6 +102,9 @@ size_t query_footprint(gbgpu_graph g, int kind, uint32_t cap_override, const gbg
     return wbfs_bytes(g->n, NB, initial_capacity(g, cap_override, o));
 }
 
+// Largest graph whose same-graph BFS queries are bit-packed together.
+constexpr int64_t kPackedMaxN = 1 << 24;
+
 struct PendingQ {
     uint64_t ticket;
     gbgpu_query q;
@@ -164,10 +168,15 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
                 gbgpu_graph g = sv->graphs[head.q.graph_id];
                 const int gid = head.q.graph_id;
                 int nsame = 0;
-                // graphs known to be deep answer BFS queries one at a time
-                // (concurrently on the workers) rather than bit-packed
-                if (head.q.kind == GBGPU_QUERY_BFS &&
-                    g->depth.load(std::memory_order_relaxed) <= kDeepGraph)
+                // BFS queries are bit-packed only on graphs a single-source
+                // search has shown to be shallow, and only up to 2^24
+                // vertices; the others run one at a time (concurrently on
+                // the workers).  Deep graphs keep 64 frontiers alive for
+                // most rounds; on RMAT scale 26, 64 bit-packed sources ran
+                // at 312 queries/s against 358 one at a time.
+                const int32_t depth = g->depth.load(std::memory_order_relaxed);
+                if (head.q.kind == GBGPU_QUERY_BFS && depth > 0 && depth <= kDeepGraph &&
+                    g->n <= kPackedMaxN)
                     for (auto& p : sv->pending)
                         if (p.q.kind == GBGPU_QUERY_BFS && p.q.graph_id == gid && nsame < 64) ++nsame;
                 // admit the largest batch of same-graph BFS queries that fits
