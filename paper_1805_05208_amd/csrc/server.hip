@@ -129,6 +129,7 @@ struct gbgpu_server_s {
     int device = 0;
     gbgpu_opts opts;
     std::vector<gbgpu_graph> graphs;
+    std::vector<uint32_t> wcap;       // per graph: bucket capacity a weighted query needed
     std::mutex mu;
     std::condition_variable cv;       // work available / memory freed / stop
     std::condition_variable cv_idle;  // everything finished
@@ -199,10 +200,16 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
                     }
                 }
                 if (taken) break;
-                const size_t nb = query_footprint(g, head.q.kind, head.cap, sv->opts);
+                // a weighted query starts with the bucket capacity an earlier
+                // query on this graph had to grow to (an overflow re-runs the
+                // whole query)
+                const uint32_t cap = head.cap ? head.cap
+                                   : head.q.kind == GBGPU_QUERY_WBFS ? sv->wcap[gid] : 0u;
+                const size_t nb = query_footprint(g, head.q.kind, cap, sv->opts);
                 if (sv->alloc.alloc(nb, &off)) {
                     bytes = nb;
                     job.push_back(head);
+                    job.back().cap = cap;
                     sv->pending.pop_front();
                     break;
                 }
@@ -251,6 +258,8 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
         } else if (requeue) {
             PendingQ p = job[0];
             p.cap = newcap;
+            uint32_t& learned = sv->wcap[p.q.graph_id];
+            learned = std::max(learned, newcap);
             sv->pending.push_front(p);
         } else {
             for (auto& p : job) finish_query(sv, p, status, rounds, t_start);
@@ -364,6 +373,7 @@ int gbgpu_server_add_graph(gbgpu_server sv, gbgpu_graph g, int32_t* graph_id) {
     if (!sv || !g || !graph_id) return set_error(GBGPU_E_INVALID, "bad argument");
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->graphs.push_back(g);
+    sv->wcap.push_back(0u);
     *graph_id = (int32_t)sv->graphs.size() - 1;
     return GBGPU_OK;
 }
