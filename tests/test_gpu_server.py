@@ -96,6 +96,39 @@ def test_server_small_arena_serialises_and_overflow_requeue(gb, graphs):
     sv.close()
 
 
+def test_server_learned_capacity_and_batching_rule(gb, graphs):
+    """A weighted query after one that had to grow its buckets starts with
+    the grown capacity; BFS queries on a graph no search has measured run one
+    at a time, later ones on the (shallow, small) graph bit-packed.  Every
+    result equals the oracle either way."""
+    gs, _ = graphs
+    g = gs[2]
+    G = gb.Graph.from_csr(g)          # fresh handle: depth not yet known
+    sv = gb.Server(arena_bytes=1 << 30, max_inflight=4, opts={"bucket_capacity": 64})
+    gid = sv.add_graph(G)
+    srcs = [int(x) for x in gg.sources(g, 12, seed=33)]
+
+    def run(kind, ss):
+        outs = []
+        for s in ss:
+            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            outs.append((sv.submit(gid, kind, s, d, p), s, d, p))
+        res = wait(sv, [o[0] for o in outs])
+        for t, s, d, p in outs:
+            assert res[t]["status"] == gb.OK
+            od, op = (oracle.bfs if kind == gb.QUERY_BFS else oracle.wbfs)(g, s)
+            dd = d.cpu().numpy() if kind == gb.QUERY_BFS else gb.as_u32(d)
+            assert np.array_equal(dd, od) and np.array_equal(p.cpu().numpy(), op), (kind, s)
+
+    run(gb.QUERY_WBFS, srcs[:1])      # overflows 64 and grows
+    run(gb.QUERY_WBFS, srcs[1:4])     # start from the grown capacity
+    run(gb.QUERY_BFS, srcs[:1])       # depth unknown: alone
+    run(gb.QUERY_BFS, srcs)           # shallow and small: packed together
+    sv.close()
+    G.free()
+
+
 def test_server_errors(gb, graphs):
     gs, Gs = graphs
     sv = gb.Server(arena_bytes=1 << 16, max_inflight=1, opts={"max_pending": 2})
