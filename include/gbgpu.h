@@ -119,7 +119,9 @@ typedef struct {
 
 /* Register a CSR graph that already lives in device memory.
  *   n          number of vertices, 0 < n < 2^31
- *   m          number of stored (directed) entries, 0 <= m <= 2^32 - 256
+ *   m          number of stored (directed) entries, 0 <= m <= 2^31 - 1 (the
+ *              kernels index edges with 32-bit unsigned integers; the largest
+ *              graph the tests run is RMAT scale 26, m = 2,103,850,106)
  *   offsets    dev int64[n+1], offsets[0] = 0, offsets[n] = m, non-decreasing
  *   neighbors  dev int32[m], each list sorted strictly ascending (no
  *              duplicates), no self loops, ids in [0, n)
@@ -354,8 +356,14 @@ typedef struct {
     int32_t status;      /* GBGPU_OK, or the query's error status          */
     int32_t rounds;      /* rounds / buckets the query took                */
     int64_t t_arrive_ns; /* CLOCK_MONOTONIC time of gbgpu_submit           */
-    int64_t t_start_ns;  /* time the query was admitted to the device      */
+    int64_t t_start_ns;  /* time the query's last run was admitted to the
+                            device (shared by the queries of one packed
+                            group)                                         */
     int64_t t_done_ns;   /* time its outputs were known complete           */
+    int32_t retries;     /* weighted BFS: runs repeated after a bucket
+                            overflow (each doubles the bucket capacity)    */
+    int32_t batch;       /* queries in the run that answered this one (1,
+                            or the size of a bit-packed same-graph group)  */
 } gbgpu_result;
 
 /* Create a server.

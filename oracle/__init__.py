@@ -49,10 +49,10 @@ WIDE_SRC = np.uint32(0xFFFFFFFF)
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c (plain C, -O2, single-threaded) into liboracle.so."""
+    """Compile oracle.c (plain C, -O3, single-threaded) into liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O3", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -41,7 +41,11 @@
  *         delta(v) = sum over children w of sigma(v) / sigma(w) * (1 +
  *         delta(w)).
  *   Widest path: W[v] = maximum over src-v paths of the smallest weight on
- *         the path (weights >= 1, uint32).
+ *         the path (weights >= 1, uint32).  The source's width is that of the
+ *         empty path, 0xFFFFFFFF; an unreachable vertex gets 0, the maximum
+ *         over no paths (the statement's "infinity when unreachable" would
+ *         collide with the source's own width).  Textbook method: Dijkstra's
+ *         algorithm on a max-heap of widths.
  *   Low-diameter decomposition (Miller-Peng-Xu, the paper's LDD algorithm
  *         box): every vertex draws a shift g(v); start(v) = max g - g(v);
  *         rounds r = 0, 1, ...: unvisited vertices with start(v) = r become
@@ -53,11 +57,7 @@
  *         below q * 2^64, q = exp(-beta), counter seed ^ (level << 40 |
  *         v << 6 | i), at most 63.
  *   Connectivity: label[v] = smallest vertex id of v's component (a FIFO
- *         BFS from each unlabelled vertex in increasing id order).  The source's width is that of the
- *         empty path, 0xFFFFFFFF; an unreachable vertex gets 0, the maximum
- *         over no paths (the statement's "infinity when unreachable" would
- *         collide with the source's own width).  Textbook method: Dijkstra's
- *         algorithm on a max-heap of widths.
+ *         BFS from each unlabelled vertex in increasing id order).
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -78,7 +78,7 @@ class Result(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
         ("t_arrive_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
-        ("t_done_ns", ctypes.c_int64),
+        ("t_done_ns", ctypes.c_int64), ("retries", ctypes.c_int32), ("batch", ctypes.c_int32),
     ]
 
 
@@ -455,7 +455,8 @@ class Server:
             return None
         _check(st)
         return {"status": r.status, "rounds": r.rounds, "t_arrive_ns": r.t_arrive_ns,
-                "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns}
+                "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns, "retries": r.retries,
+                "batch": r.batch}
 
     def drain(self):
         _check(lib().gbgpu_server_drain(self.handle))

@@ -294,7 +294,7 @@ __device__ __forceinline__ void pull_vertices(const BfsArgs& a, uint32_t r,
         }
     }
     // 2. vertices with more than four neighbours and no hit yet continue in
-    //    the list itself.  Edge indices fit in 32 bits (m < 2^32 - 256); a
+    //    the list itself.  Edge indices fit in 32 bits (m < 2^31); a
     //    vertex that does not continue gets k = lim = e.
     uint32_t e[kPullG], k[kPullG], lim[kPullG];
 #pragma unroll
@@ -708,17 +708,10 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
     }
 }
 
-// One BFS on workspace w.  The results are complete when this returns; the
-// few launches queued behind the one that found the frontier empty may still
-// be pending unless sync_end is set.  They only touch the workspace, and the
-// next run on it (on any stream) waits for them.
-int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* parent,
-               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool sync_end,
-               bool wait_prev) {
-    const double t0 = now_ms();
-    // the workspace's last user may have been another stream (not needed when
-    // the previous search ran on this same stream)
-    if (wait_prev) GB_HIP(hipStreamWaitEvent(stream, w->done, 0));
+// Kernel arguments of one BFS over workspace w (device arrays attached) with
+// its progress words and round log at prog (kHostLogOff + 4 * kLogCap words).
+static BfsArgs bfs_args(gbgpu_graph g, const BfsWs* w, uint32_t* prog, int32_t src,
+                        int32_t* dist, int32_t* parent, const gbgpu_opts& o) {
     BfsArgs a;
     a.off = g->off;
     a.nbr = g->nbr;
@@ -734,8 +727,8 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.dist = dist;
     a.parent = (uint32_t*)parent;
     a.ctl = w->ctl;
-    a.prog = w->hl.d;
-    a.log = w->hl.d + kHostLogOff;
+    a.prog = prog;
+    a.log = prog + kHostLogOff;
     a.head = g->head;
     a.nz = g->core;
     a.nz_head = g->core_head;
@@ -751,9 +744,51 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     a.force_dir = o.force_direction;
     a.light = o.pull_light;
     a.chunk_cap = (uint32_t)o.wave_chunk;
+    return a;
+}
 
+// Workgroups of a round launch: enough for the graph, at most o.grid.
+static int bfs_round_grid(gbgpu_graph g, const gbgpu_opts& o) {
     const int64_t work = std::max<int64_t>(g->nwords / 32, g->m / 4096);
-    int grid = (int)std::min<int64_t>(std::max<int64_t>(work, 1), o.grid);
+    return (int)std::min<int64_t>(std::max<int64_t>(work, 1), o.grid);
+}
+
+// Statistics of one finished BFS: bfs_stats_log adds nlog rounds of the
+// round log lg (4 words per round; see gbgpu_debug_bfs_log), bfs_stats_end
+// completes them from the progress words prog[0..3].
+static void bfs_stats_log(gbgpu_stats* st, const volatile uint32_t* lg, size_t nlog) {
+    for (size_t i = 0; i < nlog; ++i) {
+        st->rounds++;
+        if (lg[4 * i] == 2) st->pull_rounds++; else st->push_rounds++;
+        st->reached += lg[4 * i + 1];
+        st->edges_examined += lg[4 * i + 2];
+    }
+}
+
+static void bfs_stats_end(gbgpu_stats* st, const uint32_t* prog, int64_t launches,
+                          double kernel_ms, double wall_ms) {
+    // attached degree-1 vertices: counted, and one level deeper than the
+    // last round when they hang off its vertices
+    st->reached += prog[2];
+    st->rounds = std::max<int32_t>(st->rounds, (int32_t)prog[3] + 1);
+    st->launches = (int32_t)launches;
+    st->kernel_ms = kernel_ms;
+    st->wall_ms = wall_ms;
+}
+
+// One BFS on workspace w.  The results are complete when this returns; the
+// few launches queued behind the one that found the frontier empty may still
+// be pending unless sync_end is set.  They only touch the workspace, and the
+// next run on it (on any stream) waits for them.
+int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* parent,
+               const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool sync_end,
+               bool wait_prev) {
+    const double t0 = now_ms();
+    // the workspace's last user may have been another stream (not needed when
+    // the previous search ran on this same stream)
+    if (wait_prev) GB_HIP(hipStreamWaitEvent(stream, w->done, 0));
+    const BfsArgs a = bfs_args(g, w, w->hl.d, src, dist, parent, o);
+    const int grid = bfs_round_grid(g, o);
     int igrid = (int)std::min<int64_t>((g->n / 4 + kBlock - 1) / kBlock, 4096);
     if (igrid < 1) igrid = 1;
     hipLaunchKernelGGL(bfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, g->pruned,
@@ -785,27 +820,11 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     w->last_rounds = rounds;
     g->depth.store((int32_t)std::max<uint32_t>(rounds, hp[3] + 1u), std::memory_order_relaxed);
     if (st) {
+        float ms = 0.f;
+        if (o.profile) GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
         memset(st, 0, sizeof(*st));
-        if (o.profile) {
-            float ms = 0.f;
-            GB_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-            st->kernel_ms = ms;
-        }
-        const uint32_t* lg = w->hl.h + kHostLogOff;
-        int64_t reached = 0, ex = 0;
-        for (uint32_t i = 0; i < std::min<uint32_t>(rounds, (uint32_t)kLogCap); ++i) {
-            st->rounds++;
-            if (lg[4 * i] == 2) st->pull_rounds++; else st->push_rounds++;
-            reached += lg[4 * i + 1];
-            ex += lg[4 * i + 2];
-        }
-        // attached degree-1 vertices: counted, and one level deeper than the
-        // last round when they hang off its vertices
-        st->reached = reached + hp[2];
-        st->rounds = std::max<int32_t>(st->rounds, (int32_t)hp[3] + 1);
-        st->edges_examined = ex;
-        st->launches = (int32_t)launches;
-        st->wall_ms = now_ms() - t0;
+        bfs_stats_log(st, hp + kHostLogOff, std::min<uint32_t>(rounds, (uint32_t)kLogCap));
+        bfs_stats_end(st, (const uint32_t*)hp, launches, ms, now_ms() - t0);
     }
     return GBGPU_OK;
 }

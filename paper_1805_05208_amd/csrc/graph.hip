@@ -403,8 +403,8 @@ int gbgpu_load_csr(int64_t n, int64_t m, const int64_t* offsets, const int32_t* 
     if (m < 0) return set_error(GBGPU_E_INVALID, "m must be non-negative");
     if (n >= (1ll << 31) - 1)
         return set_error(GBGPU_E_UNSUPPORTED, "n = %lld exceeds 2^31 - 2", (long long)n);
-    if (m > (1ll << 32) - 256)
-        return set_error(GBGPU_E_UNSUPPORTED, "m = %lld: at most 2^32 - 256 stored edges",
+    if (m >= (1ll << 31))
+        return set_error(GBGPU_E_UNSUPPORTED, "m = %lld: at most 2^31 - 1 stored edges",
                          (long long)m);
     if (!(flags & GBGPU_SYMMETRIC))
         return set_error(GBGPU_E_INVALID,

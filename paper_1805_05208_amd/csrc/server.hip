@@ -21,6 +21,7 @@
 #include <unordered_set>
 
 #include "common.h"
+#include "admission.h"
 
 namespace gb {
 
@@ -44,50 +45,6 @@ size_t ms_pin_bytes();
 int run_ms_group_mem(const std::vector<MsQuery>& qs, void* mem, void* pin, const gbgpu_opts& o,
                      hipStream_t stream, int* rounds);
 
-// First-fit allocator over [0, size) with coalescing of free ranges.
-class ArenaAlloc {
-  public:
-    explicit ArenaAlloc(size_t size) { if (size) free_[0] = size; }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t noff = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[noff] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = (bytes + 255) & ~(size_t)255;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t largest() const {
-        size_t m = 0;
-        for (auto& kv : free_) m = std::max(m, kv.second);
-        return m;
-    }
-
-  private:
-    std::map<size_t, size_t> free_;
-};
-
 // Bucket capacity of a weighted query: the re-queue override, else the
 // option, else the default.
 static uint32_t initial_capacity(gbgpu_graph g, uint32_t cap_override, const gbgpu_opts& o) {
@@ -101,16 +58,6 @@ size_t query_footprint(gbgpu_graph g, int kind, uint32_t cap_override, const gbg
     const uint32_t NB = wbfs_window(g->maxw, o.bucket_window);
     return wbfs_bytes(g->n, NB, initial_capacity(g, cap_override, o));
 }
-
-// Largest graph whose same-graph BFS queries are bit-packed together.
-constexpr int64_t kPackedMaxN = 1 << 24;
-
-struct PendingQ {
-    uint64_t ticket;
-    gbgpu_query q;
-    int64_t t_arrive;
-    uint32_t cap;  // wBFS bucket capacity override (0 = default)
-};
 
 struct Worker {
     hipStream_t stream = nullptr;
@@ -130,6 +77,7 @@ struct gbgpu_server_s {
     gbgpu_opts opts;
     std::vector<gbgpu_graph> graphs;
     std::vector<uint32_t> wcap;       // per graph: bucket capacity a weighted query needed
+    gb::SchedEnv env;                 // admission rule's view of the graphs
     std::mutex mu;
     std::condition_variable cv;       // work available / memory freed / stop
     std::condition_variable cv_idle;  // everything finished
@@ -145,13 +93,17 @@ struct gbgpu_server_s {
 
 namespace gb {
 
-static void finish_query(gbgpu_server sv, const PendingQ& p, int status, int rounds, int64_t t_start) {
+static void finish_query(gbgpu_server sv, const PendingQ& p, int status, int rounds, int64_t t_start,
+                         int32_t batch) {
     gbgpu_result r;
+    memset(&r, 0, sizeof(r));
     r.status = status;
     r.rounds = rounds;
     r.t_arrive_ns = p.t_arrive;
     r.t_start_ns = t_start;
     r.t_done_ns = now_ns();
+    r.retries = p.retries;
+    r.batch = batch;
     sv->done[p.ticket] = r;
     sv->live.erase(p.ticket);
 }
@@ -160,60 +112,12 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
     (void)hipSetDevice(sv->device);
     std::unique_lock<std::mutex> lk(sv->mu);
     for (;;) {
-        // take the oldest query whose footprint fits now
+        // take the oldest query whose footprint fits now (with the other
+        // pending BFS queries on its graph when they can be bit-packed)
         std::vector<PendingQ> job;
         size_t off = 0, bytes = 0;
         while (!sv->stop) {
-            if (!sv->pending.empty()) {
-                const PendingQ& head = sv->pending.front();
-                gbgpu_graph g = sv->graphs[head.q.graph_id];
-                const int gid = head.q.graph_id;
-                int nsame = 0;
-                // BFS queries are bit-packed only on graphs a single-source
-                // search has shown to be shallow, and only up to 2^24
-                // vertices; the others run one at a time (concurrently on
-                // the workers).  Deep graphs keep 64 frontiers alive for
-                // most rounds; on RMAT scale 26, 64 bit-packed sources ran
-                // at 312 queries/s against 358 one at a time.
-                const int32_t depth = g->depth.load(std::memory_order_relaxed);
-                if (head.q.kind == GBGPU_QUERY_BFS && depth > 0 && depth <= kDeepGraph &&
-                    g->n <= kPackedMaxN)
-                    for (auto& p : sv->pending)
-                        if (p.q.kind == GBGPU_QUERY_BFS && p.q.graph_id == gid && nsame < 64) ++nsame;
-                // admit the largest batch of same-graph BFS queries that fits
-                // (halving from up to 64), else the oldest query alone, else
-                // wait for memory
-                bool taken = false;
-                for (int kb = nsame; kb > 1 && !taken; kb /= 2) {
-                    const size_t bb = ms_query_bytes(g->n, kb);
-                    if (sv->alloc.alloc(bb, &off)) {
-                        bytes = bb;
-                        for (auto it = sv->pending.begin(); it != sv->pending.end() && (int)job.size() < kb;) {
-                            if (it->q.kind == GBGPU_QUERY_BFS && it->q.graph_id == gid) {
-                                job.push_back(*it);
-                                it = sv->pending.erase(it);
-                            } else {
-                                ++it;
-                            }
-                        }
-                        taken = true;
-                    }
-                }
-                if (taken) break;
-                // a weighted query starts with the bucket capacity an earlier
-                // query on this graph had to grow to (an overflow re-runs the
-                // whole query)
-                const uint32_t cap = head.cap ? head.cap
-                                   : head.q.kind == GBGPU_QUERY_WBFS ? sv->wcap[gid] : 0u;
-                const size_t nb = query_footprint(g, head.q.kind, cap, sv->opts);
-                if (sv->alloc.alloc(nb, &off)) {
-                    bytes = nb;
-                    job.push_back(head);
-                    job.back().cap = cap;
-                    sv->pending.pop_front();
-                    break;
-                }
-            }
+            if (sched_admit(sv->pending, sv->alloc, sv->env, sv->wcap, &job, &off, &bytes)) break;
             sv->cv.wait(lk);
         }
         if (job.empty()) break;  // stopping
@@ -224,7 +128,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
         gbgpu_graph g = sv->graphs[job[0].q.graph_id];
         int status = GBGPU_OK, rounds = 0;
         bool requeue = false;
-        uint32_t newcap = 0;
+        uint32_t usedcap = 0;
         if (job.size() > 1) {
             std::vector<MsQuery> qs;
             for (auto& p : job) qs.push_back(MsQuery{g, p.q.src, (int32_t*)p.q.dist, p.q.parent});
@@ -246,23 +150,20 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
             rounds = st.rounds;
             if (status == GBGPU_OK && overflow) {
                 requeue = true;
-                newcap = (uint32_t)std::min<int64_t>(g->n, (int64_t)C * 2);
+                usedcap = C;
             }
         }
         lk.lock();
         sv->alloc.release(off, bytes);
         --sv->running;
-        if (requeue && query_footprint(g, GBGPU_QUERY_WBFS, newcap, sv->opts) > sv->arena_bytes) {
-            // the larger buckets can never be admitted: fail the query
-            finish_query(sv, job[0], GBGPU_E_NOMEM, rounds, t_start);
-        } else if (requeue) {
-            PendingQ p = job[0];
-            p.cap = newcap;
-            uint32_t& learned = sv->wcap[p.q.graph_id];
-            learned = std::max(learned, newcap);
-            sv->pending.push_front(p);
+        if (requeue) {
+            // re-queued at the front with twice the buckets; failed when the
+            // larger workspace could never be admitted
+            if (!sched_requeue_overflow(sv->pending, sv->env, sv->wcap, sv->arena_bytes, job[0],
+                                        usedcap, g->n))
+                finish_query(sv, job[0], GBGPU_E_NOMEM, rounds, t_start, 1);
         } else {
-            for (auto& p : job) finish_query(sv, p, status, rounds, t_start);
+            for (auto& p : job) finish_query(sv, p, status, rounds, t_start, (int32_t)job.size());
         }
         sv->cv.notify_all();
         if (sv->pending.empty() && sv->running == 0) sv->cv_idle.notify_all();
@@ -338,6 +239,23 @@ int gbgpu_server_create(void* arena, size_t arena_bytes, int32_t max_inflight, c
     sv->alloc = ArenaAlloc(arena_bytes & ~(size_t)255);
     sv->opts = resolve_opts(o);
     if (sv->opts.max_pending > 0) sv->max_pending = (size_t)sv->opts.max_pending;
+    // BFS queries are bit-packed only on graphs a single-source search has
+    // shown to be shallow, and only up to 2^24 vertices; the others run one
+    // at a time (concurrently on the workers).  Deep graphs keep 64
+    // frontiers alive for most rounds; on RMAT scale 26, 64 bit-packed
+    // sources ran at 312 queries/s against 358 one at a time.  The graph
+    // list is only read under the server's lock.
+    sv->env.packable = [sv](int32_t gid) {
+        gbgpu_graph g = sv->graphs[gid];
+        const int32_t depth = g->depth.load(std::memory_order_relaxed);
+        return depth > 0 && depth <= kDeepGraph && g->n <= kPackedMaxN;
+    };
+    sv->env.footprint = [sv](int32_t gid, int32_t kind, uint32_t cap) {
+        return query_footprint(sv->graphs[gid], kind, cap, sv->opts);
+    };
+    sv->env.packed_bytes = [sv](int32_t gid, int64_t k) {
+        return ms_query_bytes(sv->graphs[gid]->n, k);
+    };
     if (hipGetDevice(&sv->device) != hipSuccess) {
         delete sv;
         return set_error(GBGPU_E_HIP, "hipGetDevice failed");
@@ -405,6 +323,7 @@ int gbgpu_submit(gbgpu_server sv, const gbgpu_query* q, uint64_t* ticket) {
     p.q = *q;
     p.t_arrive = t;
     p.cap = 0;
+    p.retries = 0;
     sv->pending.push_back(p);
     sv->live.insert(p.ticket);
     *ticket = p.ticket;

@@ -141,7 +141,7 @@ def test_torus256_bellman_ford_and_widest_path(gb):
 
 @pytest.mark.parametrize("which", ["rmat24", "torus256"])
 def test_betweenness(gb, which, request):
-    from test_gpu_bc import assert_close, rtol_for
+    from test_gpu_bc import assert_close, oracle_levels, rtol_for
     if which == "rmat24":
         g, _, G = request.getfixturevalue("rmat24")
         s = int(gg.sources(g, 16, seed=3)[0])
@@ -151,9 +151,9 @@ def test_betweenness(gb, which, request):
         G = gb.Graph.from_csr(g, validate=False, with_weights=False)
         s = int(gg.sources(g, 1, seed=3)[0])
         own = True
-    dep, st = gb.betweenness(G, s, stats=True)
+    dep = gb.betweenness(G, s)
     exp = oracle.betweenness(g, s)
-    assert_close(dep.cpu().numpy(), exp, rtol_for(g, st["rounds"]), f"{which} src={s}")
+    assert_close(dep.cpu().numpy(), exp, rtol_for(g, oracle_levels(g, s)), f"{which} src={s}")
     if own:
         G.free()
 

@@ -120,11 +120,25 @@ def test_server_learned_capacity_and_batching_rule(gb, graphs):
             od, op = (oracle.bfs if kind == gb.QUERY_BFS else oracle.wbfs)(g, s)
             dd = d.cpu().numpy() if kind == gb.QUERY_BFS else gb.as_u32(d)
             assert np.array_equal(dd, od) and np.array_equal(p.cpu().numpy(), op), (kind, s)
+        return [res[o[0]] for o in outs]
 
-    run(gb.QUERY_WBFS, srcs[:1])      # overflows 64 and grows
-    run(gb.QUERY_WBFS, srcs[1:4])     # start from the grown capacity
-    run(gb.QUERY_BFS, srcs[:1])       # depth unknown: alone
-    run(gb.QUERY_BFS, srcs)           # shallow and small: packed together
+    first = run(gb.QUERY_WBFS, srcs[:1])      # overflows 64 and grows
+    assert first[0]["retries"] >= 1 and first[0]["batch"] == 1
+    # the same source again starts from the capacity it grew to: no rerun
+    again = run(gb.QUERY_WBFS, srcs[:1] * 2)
+    assert [r["retries"] for r in again] == [0, 0]
+    run(gb.QUERY_WBFS, srcs[1:4])
+    alone = run(gb.QUERY_BFS, srcs[:1])       # depth unknown: alone
+    assert alone[0]["batch"] == 1
+    packed = run(gb.QUERY_BFS, srcs)          # shallow and small: packed together
+    assert max(r["batch"] for r in packed) > 1
+    # the queries of one packed run share its start time, and their number
+    # is the batch size each of them reports
+    by_start = {}
+    for r in packed:
+        by_start.setdefault(r["t_start_ns"], []).append(r["batch"])
+    for bs in by_start.values():
+        assert all(b == len(bs) for b in bs), by_start
     sv.close()
     G.free()
 
