@@ -177,6 +177,28 @@ int gbgpu_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist,
                    int32_t* parent, int64_t row_stride, const gbgpu_opts* o,
                    gbgpu_stats* st, void* stream);
 
+/* Allocation-free single-source BFS, for callers that cannot allocate
+ * device or pinned host memory during the call (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation).  Same algorithm,
+ * kernels and results as gbgpu_bfs; the traversal workspace, progress words
+ * and round log live in a library-owned static device array of 64 MiB per
+ * device (held from the library's first use on that device until the
+ * process ends), so the graph's workspace is never allocated.
+ *   n limit   at most about 3.9 million vertices: the workspace takes
+ *             16 n + 0.4 n / 8 bytes plus about 170 KB of control words
+ *   other arguments as gbgpu_bfs; st->kernel_ms is always 0 (no events)
+ * The host checks for the end of the search by copying four progress words
+ * back after every max(8, rounds_per_sync) round launches and synchronising
+ * the stream, so the call returns with the stream drained.  Calls for one
+ * device share its array: the library serialises them (one at a time per
+ * device and process); the array keeps the last call's contents, which the
+ * next call re-initialises.  The current device must be the graph's.
+ * Errors: as gbgpu_bfs; E_UNSUPPORTED when the graph needs more workspace
+ * than the array holds (nothing is launched), E_INVALID when the current
+ * device is not the one the graph was loaded on. */
+int gbgpu_bfs_noalloc(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+                      const gbgpu_opts* o, gbgpu_stats* st, void* stream);
+
 /* Single-source integral-weight SSSP (weighted BFS problem statement; the
  * paper's wBFS algorithm box: buckets by distance, edgeMapData relaxations
  * with priority-write).

@@ -29,7 +29,7 @@ EXPORTED = [
     "gbgpu_graph_info", "gbgpu_bfs", "gbgpu_wbfs", "gbgpu_bellman_ford", "gbgpu_widest_path",
     "gbgpu_bc", "gbgpu_ldd", "gbgpu_connectivity",
     "gbgpu_compress", "gbgpu_decompress", "gbgpu_bfs_compressed", "gbgpu_bfs_simple",
-    "gbgpu_bfs_many",
+    "gbgpu_bfs_many", "gbgpu_bfs_noalloc",
     "gbgpu_bfs_multi", "gbgpu_bfs_batch",
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
             "gbgpu_graph_info": ([P, P, P, P], ctypes.c_int),
             "gbgpu_bfs": ([P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bfs_many": ([P, P, I32, P, P, I64, P, P, P], ctypes.c_int),
+            "gbgpu_bfs_noalloc": ([P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_wbfs": ([P, I32, P, P, P, P, P], ctypes.c_int),
             "gbgpu_bellman_ford": ([P, I32, P, P, P, P], ctypes.c_int),
             "gbgpu_widest_path": ([P, I32, P, P, P, P], ctypes.c_int),
@@ -264,6 +265,20 @@ def bfs(g: Graph, src: int, dist=None, parent=None, opts=None, stream=None,
     _check(lib().gbgpu_bfs(g.handle, int(src), ctypes.c_void_p(dist.data_ptr()),
                            ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats),
                            _stream_ptr(stream)))
+    return (dist, parent, st.as_dict()) if stats else (dist, parent)
+
+
+def bfs_noalloc(g: Graph, src: int, dist, parent, opts=None, stream=None, stats: bool = False):
+    """Single-source BFS through the allocation-free entry point (workspace
+    in the library's static device array).  dist and parent are
+    caller-provided int32[n] device tensors."""
+    dist = _out(dist, g.n, torch.int32)
+    parent = _out(parent, g.n, torch.int32)
+    oref, _keep = _opts_ref(opts)
+    st = Stats()
+    _check(lib().gbgpu_bfs_noalloc(g.handle, int(src), ctypes.c_void_p(dist.data_ptr()),
+                                   ctypes.c_void_p(parent.data_ptr()), oref, _st_ref(st, stats),
+                                   _stream_ptr(stream)))
     return (dist, parent, st.as_dict()) if stats else (dist, parent)
 
 

@@ -878,4 +878,101 @@ int bfs_round_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nro
     return GBGPU_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free BFS (gbgpu_bfs_noalloc): the same kernels, with the
+// workspace, progress words and round log in one file-scope device array
+// instead of memory allocated per graph.  The host learns of the end of the
+// search by copying the progress words back every few launches (there is no
+// pinned memory to poll).  Launches queued past the end find an empty
+// frontier and return at once, as in the pipelined driver.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr size_t kScratchProgBytes = (kHostLogOff + 4 * (size_t)kLogCap) * 4;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex s_scratch_mu[kMaxDevices];  // one call at a time per device
+static void* s_scratch_ptr[kMaxDevices];      // device address of `scratch`, per device
+
+size_t bfs_noalloc_ws_bytes(int64_t n, int64_t nwords) {
+    return al256(kScratchProgBytes) + bfs_ws_bytes(n, nwords);
+}
+
+// Clears the progress words before the first round launch.
+__global__ void bfs_prog_clear_kernel(uint32_t* prog) {
+    if (threadIdx.x < 4) prog[threadIdx.x] = 0u;
+}
+
+int run_bfs_noalloc(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+                    const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream) {
+    const double t0 = now_ms();
+    int dev = 0;
+    GB_HIP(hipGetDevice(&dev));
+    if (dev != g->device)
+        return set_error(GBGPU_E_INVALID, "current device %d is not the graph's device %d", dev,
+                         g->device);
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(GBGPU_E_UNSUPPORTED, "device %d beyond the library's %d", dev,
+                         kMaxDevices);
+    const size_t need = bfs_noalloc_ws_bytes(g->n, g->nwords);
+    if (need > kScratchBytes)
+        return set_error(GBGPU_E_UNSUPPORTED,
+                         "n = %lld needs %zu bytes of workspace; the allocation-free BFS "
+                         "holds %zu",
+                         (long long)g->n, need, kScratchBytes);
+    std::lock_guard<std::mutex> lk(s_scratch_mu[dev]);
+    if (!s_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        GB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(GBGPU_E_HIP, "no device address for the BFS scratch array");
+        s_scratch_ptr[dev] = ptr;
+    }
+    char* base = (char*)s_scratch_ptr[dev];
+    uint32_t* prog = (uint32_t*)base;
+    BfsWs w;  // device arrays only: no host log, events or owned block
+    bfs_ws_attach(&w, base + al256(kScratchProgBytes), g->n, g->nwords);
+    const BfsArgs a = bfs_args(g, &w, prog, src, dist, parent, o);
+    const int grid = bfs_round_grid(g, o);
+    int igrid = (int)std::min<int64_t>((g->n / 4 + kBlock - 1) / kBlock, 4096);
+    if (igrid < 1) igrid = 1;
+    hipLaunchKernelGGL(bfs_prog_clear_kernel, dim3(1), dim3(64), 0, stream, prog);
+    hipLaunchKernelGGL(bfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, g->pruned,
+                       (uint32_t)src);
+    GB_HIP(hipGetLastError());
+    const int64_t max_rounds = std::min<int64_t>(g->n + 2, 0x7FFFFFFF);
+    const int64_t per_check = std::max(8, o.rounds_per_sync);
+    uint32_t hp[4] = {0, 0, 0, 0};
+    int64_t launches = 0;
+    while (launches < max_rounds) {
+        const int64_t upto = std::min(max_rounds, launches + per_check);
+        for (; launches < upto; ++launches)
+            hipLaunchKernelGGL(bfs_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, a,
+                               (uint32_t)launches);
+        GB_HIP(hipGetLastError());
+        GB_HIP(hipMemcpyAsync(hp, prog, sizeof(hp), hipMemcpyDeviceToHost, stream));
+        GB_HIP(hipStreamSynchronize(stream));
+        if (hp[1]) break;
+    }
+    if (!hp[1])
+        return set_error(GBGPU_E_HIP, "traversal did not finish within %lld launches",
+                         (long long)max_rounds);
+    const uint32_t rounds = hp[1] - 1;
+    g->depth.store((int32_t)std::max<uint32_t>(rounds, hp[3] + 1u), std::memory_order_relaxed);
+    if (st) {
+        // the round log, copied back 256 rounds at a time into a stack buffer
+        memset(st, 0, sizeof(*st));
+        uint32_t lg[4 * 256];
+        const size_t nlog = std::min<size_t>(rounds, (size_t)kLogCap);
+        for (size_t i = 0; i < nlog; i += 256) {
+            const size_t c = std::min<size_t>(256, nlog - i);
+            GB_HIP(hipMemcpyAsync(lg, prog + kHostLogOff + 4 * i, c * 16, hipMemcpyDeviceToHost,
+                                  stream));
+            GB_HIP(hipStreamSynchronize(stream));
+            bfs_stats_log(st, lg, c);
+        }
+        bfs_stats_end(st, hp, launches, 0.0, now_ms() - t0);
+    }
+    return GBGPU_OK;
+}
+
 }  // namespace gb

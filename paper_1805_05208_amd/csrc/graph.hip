@@ -137,6 +137,8 @@ int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gb
             gbgpu_stats* st, hipStream_t stream);
 int run_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist, int32_t* parent,
                  int64_t stride, const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream);
+int run_bfs_noalloc(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+                    const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream);
 int run_wbfs(gbgpu_graph g, int32_t src, uint32_t* dist, int32_t* parent, const gbgpu_opts& o,
              gbgpu_stats* st, hipStream_t stream);
 int bfs_round_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_t* nrounds);
@@ -529,6 +531,16 @@ int gbgpu_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const 
     gbgpu_opts opt = resolve_opts(o);
     std::lock_guard<std::mutex> lk(g->mu);
     return run_bfs(g, src, dist, parent, opt, st, (hipStream_t)stream);
+}
+
+int gbgpu_bfs_noalloc(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent,
+                      const gbgpu_opts* o, gbgpu_stats* st, void* stream) {
+    if (!g) return set_error(GBGPU_E_INVALID, "graph is NULL");
+    if (!dist || !parent) return set_error(GBGPU_E_INVALID, "dist/parent is NULL");
+    if (src < 0 || src >= g->n)
+        return set_error(GBGPU_E_INVALID, "src %d out of range [0, %lld)", src, (long long)g->n);
+    gbgpu_opts opt = resolve_opts(o);
+    return run_bfs_noalloc(g, src, dist, parent, opt, st, (hipStream_t)stream);
 }
 
 int gbgpu_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist,
