@@ -122,6 +122,69 @@ def bfs_bytes(g, keys, dist, parent, rlog):
     return total, per_round
 
 
+def host_cpu():
+    """CPU model, logical CPU count and the CPUs this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def pinned_median(fn, reps=3):
+    """Median wall time of fn() over reps runs with the calling thread pinned
+    to one host CPU (the last one this process may use); the previous
+    affinity is restored afterwards.  Returns (median seconds, cpu)."""
+    allowed = sorted(os.sched_getaffinity(0))
+    cpu = allowed[-1]
+    os.sched_setaffinity(0, {cpu})
+    try:
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    return float(np.median(ts)), cpu
+
+
+def oracle_all_cores(calls, threads):
+    """Independent oracle queries, one per host thread (the oracle's C calls
+    release the interpreter lock): (queries per second, wall seconds)."""
+    import concurrent.futures as cf
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda c: c(), calls))
+    wall = time.perf_counter() - t
+    return len(calls) / wall, wall
+
+
+def copy_peak_gbs(torch, nbytes=1 << 30, reps=5):
+    """Streaming-copy rate of this GPU (read + write bytes of a 1 GiB device
+    copy per second, best of reps, timed with HIP events)."""
+    x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = 1e30
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,7 +201,8 @@ def main():
                     help="print per-kernel averages of a rocprofv3 --pmc csv directory and exit")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
-    ap.add_argument("--only", choices=["connectivity", "compressed", "wbfs", "sssp", "bc"],
+    ap.add_argument("--only", choices=["connectivity", "compressed", "wbfs", "sssp", "bc",
+                                       "serving", "batched"],
                     default="",
                     help="time only the given section (for profiling) and print its own JSON line")
     args = ap.parse_args()
@@ -188,6 +252,15 @@ def main():
         for s in srcs4:
             d, _ = gb.bfs(G, s)
             edges += int(deg[d.cpu().numpy() != 2**31 - 1].sum()) // 2
+        if args.only == "wbfs":
+            # the step log of one search per source (bucket, entries, degree
+            # sum, kind: 0 push, 1 mark, 2 pull), in launch order, for
+            # joining with a kernel trace
+            logs = {}
+            for s in srcs4:
+                gb.wbfs(Gw, s)
+                logs[str(s)] = Gw.wbfs_log().tolist()
+            res["step_logs"] = logs
         for key, fn, _gr in runs:
             for _ in range(args.warmup):
                 for s in srcs4:
@@ -231,6 +304,36 @@ def main():
             res[f"{key}_gteps"] = round(edges / dt / 1e9, 2)
             res[f"{key}_ms_per_source"] = round(dt * 1e3 / len(srcs), 3)
             log(f"{key}: {res[f'{key}_ms_per_source']} ms/source, {res[f'{key}_gteps']} GTEPS")
+        print(json.dumps(res), flush=True)
+        return
+    if args.only == "batched":
+        # 64 seeded sources in one gbgpu_bfs_multi call against the same
+        # sources one gbgpu_bfs call each; --steps timed repetitions
+        s64 = [int(x) for x in gg.sources(g, 64, seed=3)]
+        gb.bfs(G, s64[0])
+        D, P = gb.bfs_multi(G, s64)
+        d1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        p1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        res = {"metric": "batched_section", "config": {"workload": f"rmat{args.scale}",
+                                                       "sources": 64}}
+        for key, fn in (("batched64", lambda: gb.bfs_multi(G, s64, dist=D, parent=P)),
+                        ("single", lambda: [gb.bfs(G, s, dist=d1, parent=p1) for s in s64])):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / max(args.steps, 1)
+            res[f"{key}_ms"] = round(dt * 1e3, 3)
+            res[f"{key}_qps"] = round(64 / dt, 1)
+            log(f"{key}: {dt * 1e3:.3f} ms for 64 sources, {64 / dt:.1f} q/s")
+        print(json.dumps(res), flush=True)
+        return
+    if args.only == "serving":
+        res = {"metric": "serving_section", "config": {"workload": "six resident graphs"}}
+        res.update(run_serving(g, G, gg, gb, torch))
         print(json.dumps(res), flush=True)
         return
     if args.only == "connectivity":
@@ -310,6 +413,26 @@ def main():
     torch.cuda.synchronize()
     per_call_gteps = step_edges * args.steps / (time.perf_counter() - t1) / 1e9
     log(f"BFS with one call per source: {per_call_gteps:.1f} GTEPS")
+    # each source timed on its own: median of 5 calls, HIP events on the
+    # stream around each call (per-source GTEPS and their harmonic mean)
+    per_src_ms = []
+    for s in srcs:
+        ts = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            gb.bfs(G, s, dist=dist, parent=parent, opts=user_opts)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        per_src_ms.append(float(np.median(ts)))
+    per_src_gteps = [he / (ms * 1e-3) / 1e9 for he, ms in zip(half_edges, per_src_ms)]
+    hmean_gteps = len(per_src_gteps) / sum(1.0 / x for x in per_src_gteps)
+    log(f"per-source GTEPS (median of 5 each): min {min(per_src_gteps):.1f} max "
+        f"{max(per_src_gteps):.1f}, harmonic mean {hmean_gteps:.1f}")
+    copy_gbs = copy_peak_gbs(torch)
+    log(f"streaming copy: {copy_gbs:.0f} GB/s (read + write)")
 
     # --- the same steps again, each BFS's round-kernel launches bracketed by
     # two HIP events on the library's stream (profile=1).  Reading the events
@@ -347,25 +470,40 @@ def main():
         "bytes_per_launch": alg_bytes / max(launches, 1),
         "avg_launch_us": kernel_ms * 1e3 / max(launches, 1),
         "launches": launches,
+        # the same bytes against the measured streaming-copy rate, and over
+        # the whole step's wall time (init, tails and gaps included)
+        "copy_peak_gbs": round(copy_gbs, 1),
+        "frac_of_copy_peak": round(achieved / copy_gbs, 4) if achieved else None,
+        "frac_wall": round(alg_bytes / (wall * 1e9) / HBM_PEAK_GBS, 4),
     }
     roof["traffic"] = measured_traffic("bfs_round_kernel_rmat24_traffic.md")
 
     # --- CPU baseline: the oracle on a bounded sample ---------------------------
+    # sequential C oracle (-O3), one thread pinned to one host CPU, median of
+    # 3 runs per source, two of the timed sources (about 25 s on the host)
     cpu = None
     if not args.no_cpu:
         import oracle
         nsamp = 2
-        t = time.perf_counter()
+        meds = []
+        pin = None
         for i in range(nsamp):
             od, op = oracle.bfs(g, srcs[i])
             assert np.array_equal(od, outs[i][0]) and np.array_equal(op, outs[i][1]), \
                 "GPU BFS differs from the oracle"
-        ct = time.perf_counter() - t
+            t_med, pin = pinned_median(lambda: oracle.bfs(g, srcs[i]), reps=3)
+            meds.append(t_med)
+        ct = sum(meds)
+        hc = host_cpu()
         cpu = {"value": round(sum(half_edges[:nsamp]) / ct / 1e9, 4), "unit": "GTEPS", "cores": 1,
                "kind": "oracle",
-               "sample": f"sequential BFS + min-ID parent pass from {nsamp} of the {len(srcs)} "
-                         f"sources on rmat{args.scale} ({ct:.1f} s)"}
-        log(f"oracle: {cpu['value']} GTEPS on one core; GPU results identical on the sample")
+               "sample": f"sequential BFS + min-ID parent pass (C, -O3) from {nsamp} of the "
+                         f"{len(srcs)} sources on rmat{args.scale}, median of 3 runs each, "
+                         f"thread pinned to CPU {pin} ({ct:.1f} s of medians)",
+               "host_cpu": hc["model"], "host_nproc": hc["nproc"],
+               "host_cpus_allowed": hc["affinity"]}
+        log(f"oracle: {cpu['value']} GTEPS on one pinned core of {hc['model']} "
+            f"({hc['nproc']} CPUs); GPU results identical on the sample")
 
     extra = {}
     if not args.no_extra:
@@ -392,6 +530,9 @@ def main():
         "cpu_baseline": cpu,
         "opts": user_opts,
         "gteps_one_call_per_source": round(per_call_gteps, 2),
+        "per_source_gteps": [round(x, 1) for x in per_src_gteps],
+        "per_source_ms": [round(x, 4) for x in per_src_ms],
+        "harmonic_mean_gteps": round(hmean_gteps, 2),
         "extra": extra,
     }
     print(json.dumps(line), flush=True)
@@ -534,6 +675,14 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         extra["batched64_qps"] = round(64 / tb, 1)
         extra["single_qps"] = round(64 / t1, 1)
         log(f"batched 64: {extra['batched64_qps']} q/s vs one-at-a-time {extra['single_qps']} q/s")
+        # the oracle on every host core: independent BFS queries of the
+        # batch, one per thread
+        import oracle
+        thr = min(16, len(os.sched_getaffinity(0)))
+        qps, wall = oracle_all_cores([lambda s=s: oracle.bfs(g, s) for s in s64[:thr]], thr)
+        extra["oracle_all_cores_batched_qps"] = round(qps, 3)
+        extra["oracle_all_cores_threads"] = thr
+        log(f"oracle on {thr} host threads: {qps:.2f} BFS/s on rmat24 ({wall:.1f} s)")
         del Gw
     except Exception as ex:  # noqa: BLE001 - extras must not hide the headline
         extra["error_rmat"] = repr(ex)[:300]
@@ -611,13 +760,132 @@ def run_uneven_batch(gg, gb):
     return out
 
 
-def run_serving(g, G, gg, gb, torch, nq=400):
-    """Poisson arrivals of mixed BFS/wBFS queries on resident graphs."""
+class ServedMix:
+    """Drives the server with a seeded mix of BFS / weighted BFS queries on
+    the resident graphs.  Each in-flight query has its own output pair from
+    a per-graph pool; a pair is reused only after its ticket was polled, its
+    status checked and its outputs verified against the standalone call
+    (a digest of dist and parent for every query; element by element for
+    the queries whose source is one of the first two of its graph)."""
+
+    POOL = 24
+    NSRC = 32
+
+    def __init__(self, graphs, sv, ids, gg, gb, torch):
+        self.graphs, self.sv, self.ids, self.gb, self.torch = graphs, sv, ids, gb, torch
+        self.srcsets = [[int(x) for x in gg.sources(h, self.NSRC, seed=3)] for _, h, _ in graphs]
+        self.free = {gi: list(range(self.POOL)) for gi in range(len(graphs))}
+        self.bufs = {gi: [(torch.empty(h.n, dtype=torch.int32, device="cuda"),
+                           torch.empty(h.n, dtype=torch.int32, device="cuda"))
+                          for _ in range(self.POOL)] for gi, (_, h, _) in enumerate(graphs)}
+        self.mult = {}
+        self.digest_ref = {}
+        self.full_ref = {}
+        self.out = {}        # ticket -> (gi, kind, si, buf index)
+        self.records = []    # per finished query: gi, kind, latency ms, retries, batch
+        self.verified_full = 0
+        self.verified_digest = 0
+        self.pool_waits = 0
+
+    def digest(self, gi, d, p):
+        torch = self.torch
+        if gi not in self.mult:
+            n = d.numel()
+            i = torch.arange(n, device="cuda", dtype=torch.int64)
+            self.mult[gi] = ((i * 2654435761) % 2147483647 + 1, (i * 40503 + 12345) % 1000003 + 1)
+        m1, m2 = self.mult[gi]
+        dl = d.to(torch.int64) & 0xFFFFFFFF
+        pl = p.to(torch.int64)
+        return tuple(int(x) for x in torch.stack(
+            [(dl * m1).sum(), (pl * m2).sum(), dl.sum(), pl.sum()]).cpu())
+
+    def references(self):
+        """Standalone results (gbgpu_bfs / gbgpu_wbfs) of every source a
+        query can draw: digests, and full copies for the first two sources."""
+        gb, torch = self.gb, self.torch
+        for gi, (_, h, Gh) in enumerate(self.graphs):
+            for kind in (0, 1):
+                for si, s in enumerate(self.srcsets[gi]):
+                    d, p = (gb.bfs if kind == 0 else gb.wbfs)(Gh, s)
+                    self.digest_ref[(gi, kind, si)] = self.digest(gi, d, p)
+                    if si < 2:
+                        self.full_ref[(gi, kind, si)] = (d, p)
+        torch.cuda.synchronize()
+
+    def submit(self, gi, kind, si):
+        while not self.free[gi]:
+            self.pool_waits += 1
+            self.harvest(block=True)
+        b = self.free[gi].pop()
+        d, p = self.bufs[gi][b]
+        t = self.sv.submit(self.ids[gi], kind, self.srcsets[gi][si], d, p)
+        self.out[t] = (gi, kind, si, b)
+
+    def harvest(self, block=False):
+        """Polls the outstanding tickets once (block: until one finished)."""
+        while True:
+            done = []
+            for t in list(self.out):
+                r = self.sv.poll(t)
+                if r is not None:
+                    done.append((t, r))
+            for t, r in done:
+                gi, kind, si, b = self.out.pop(t)
+                assert r["status"] == 0, (self.graphs[gi][0], kind, r)
+                d, p = self.bufs[gi][b]
+                assert self.digest(gi, d, p) == self.digest_ref[(gi, kind, si)], \
+                    f"served {self.graphs[gi][0]} kind {kind} src #{si} differs from standalone"
+                self.verified_digest += 1
+                if si < 2:
+                    rd, rp = self.full_ref[(gi, kind, si)]
+                    assert self.torch.equal(d, rd) and self.torch.equal(p, rp)
+                    self.verified_full += 1
+                self.records.append((gi, kind, (r["t_done_ns"] - r["t_arrive_ns"]) / 1e6,
+                                     r["retries"], r["batch"]))
+                self.free[gi].append(b)
+            if done or not block or not self.out:
+                return
+            time.sleep(0.0002)
+
+    def finish(self):
+        self.sv.drain()
+        while self.out:
+            self.harvest(block=True)
+
+    def draw(self, rng):
+        return (int(rng.integers(0, len(self.graphs))), int(rng.integers(0, 2)),
+                int(rng.integers(0, self.NSRC)))
+
+    def summary(self, records):
+        lat = np.array([r[2] for r in records])
+        out = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        per = {}
+        for gi, (name, _, _) in enumerate(self.graphs):
+            for kind, kname in ((0, "bfs"), (1, "wbfs")):
+                sel = [r for r in records if r[0] == gi and r[1] == kind]
+                if not sel:
+                    continue
+                l = np.array([r[2] for r in sel])
+                per[f"{name}_{kname}"] = {
+                    "n": len(sel), "p50_ms": round(float(np.percentile(l, 50)), 3),
+                    "p99_ms": round(float(np.percentile(l, 99)), 3),
+                    "retried": int(sum(1 for r in sel if r[3] > 0)),
+                    "packed": int(sum(1 for r in sel if r[4] > 1))}
+        out["per_graph_kind"] = per
+        return out
+
+
+def run_serving(g, G, gg, gb, torch, nq=2000):
+    """Poisson arrivals of mixed BFS / weighted BFS queries on the six
+    resident graphs, at 0.5x and 0.8x of the saturated rate, every served
+    result verified against the standalone call."""
     # six resident graphs, weights uniform in [1, log2 n): RMAT scales 18,
     # 22, 24 and 26, the 256^3 torus, Erdos-Renyi 2^23 vertices of average
     # degree 32
     w24 = gg.weights(g, 24, seed=2)
-    graphs = [(g, gb.Graph(G.offsets, G.nbrs, w24, validate=False))]
+    graphs = [("rmat24", g, gb.Graph(G.offsets, G.nbrs, w24, validate=False))]
+    hosts = {"rmat24": (g, w24)}
     for name, make, W in (("rmat18", lambda: gg.rmat(18, seed=1), 18),
                           ("rmat22", lambda: gg.rmat(22, seed=1), 22),
                           ("rmat26", lambda: gg.rmat(26, seed=1), 26),
@@ -625,71 +893,97 @@ def run_serving(g, G, gg, gb, torch, nq=400):
                           ("er23", lambda: gg.erdos_renyi(1 << 23, 32, seed=1), 23)):
         t = time.perf_counter()
         h = make().with_weights(W, seed=2)
-        graphs.append((h, gb.Graph.from_csr(h, validate=False)))
+        graphs.append((name, h, gb.Graph.from_csr(h, validate=False)))
+        hosts[name] = (h, h.weights)
         log(f"serving graph {name}: n={h.n} m={h.m} loaded in {time.perf_counter() - t:.1f}s")
     # a weighted BFS on RMAT-26 takes ~9 GB of workspace (64 buckets of n/4)
     sv = gb.Server(arena_bytes=96 << 30, max_inflight=8)
-    ids = [sv.add_graph(GG) for _, GG in graphs]
+    ids = [sv.add_graph(GG) for _, _, GG in graphs]
+    mix = ServedMix(graphs, sv, ids, gg, gb, torch)
+    t = time.perf_counter()
+    mix.references()
+    log(f"serving: standalone references of {len(mix.digest_ref)} (graph, kind, source) in "
+        f"{time.perf_counter() - t:.1f}s")
     rng = np.random.default_rng(7)
-    srcsets = [gg.sources(h, 32, seed=3) for h, _ in graphs]
-    bufs = {}
-    for gi, (h, _) in enumerate(graphs):
-        bufs[gi] = [(torch.empty(h.n, dtype=torch.int32, device="cuda"),
-                     torch.empty(h.n, dtype=torch.int32, device="cuda")) for _ in range(16)]
-    # saturated throughput first: submit everything at once
+
+    # saturated throughput: the whole burst submitted at once (as far as the
+    # output pools allow)
     def burst(count):
-        ts = []
         t0 = time.perf_counter()
-        for i in range(count):
-            gi = int(rng.integers(0, len(graphs)))
-            kind = int(rng.integers(0, 2))
-            d, p = bufs[gi][i % 16]
-            ts.append(sv.submit(ids[gi], kind, int(srcsets[gi][i % 32]), d, p))
-        sv.drain()
-        for t in ts:
-            sv.poll(t)
+        for _ in range(count):
+            mix.submit(*mix.draw(rng))
+        mix.finish()
         return count / (time.perf_counter() - t0)
-    qps_sat = burst(nq // 2)
+    burst(48)  # warm-up: every graph's workspaces and depth known
+    mix.records.clear()
+    w0 = mix.pool_waits
+    qps_sat = burst(600)
+    sat_records = list(mix.records)
+    sat_waits = mix.pool_waits - w0
 
     # the same kind of mix one query at a time through gbgpu_bfs / gbgpu_wbfs
     def one_at_a_time(count):
         r2 = np.random.default_rng(7)
         t0 = time.perf_counter()
-        for i in range(count):
-            gi = int(r2.integers(0, len(graphs)))
-            kind = int(r2.integers(0, 2))
-            d, p = bufs[gi][i % 16]
-            fn = gb.bfs if kind == 0 else gb.wbfs
-            fn(graphs[gi][1], int(srcsets[gi][i % 32]), dist=d, parent=p)
+        for _ in range(count):
+            gi, kind, si = mix.draw(r2)
+            d, p = mix.bufs[gi][0]
+            (gb.bfs if kind == 0 else gb.wbfs)(graphs[gi][2], mix.srcsets[gi][si], dist=d, parent=p)
         torch.cuda.synchronize()
         return count / (time.perf_counter() - t0)
-    qps_single = one_at_a_time(nq // 2)
-    lam = 0.5 * qps_sat
-    lat = []
-    pend = []
-    t0 = time.perf_counter()
-    tnext = t0
-    for i in range(nq):
-        tnext += rng.exponential(1.0 / lam)
-        while time.perf_counter() < tnext:
-            pass
-        gi = int(rng.integers(0, len(graphs)))
-        kind = int(rng.integers(0, 2))
-        d, p = bufs[gi][i % 16]
-        pend.append(sv.submit(ids[gi], kind, int(srcsets[gi][i % 32]), d, p))
-    sv.drain()
-    el = time.perf_counter() - t0
-    for t in pend:
-        r = sv.poll(t)
-        lat.append((r["t_done_ns"] - r["t_arrive_ns"]) / 1e6)
-    sv.close()
-    lat = np.array(lat)
+    qps_single = one_at_a_time(300)
+    log(f"serving: saturated {qps_sat:.1f} q/s, one at a time {qps_single:.1f} q/s")
+
     res = {"serving_saturated_qps": round(qps_sat, 1), "serving_single_qps": round(qps_single, 1),
-           "serving_lambda_qps": round(lam, 1),
-           "serving_qps": round(nq / el, 1), "serving_p50_ms": round(float(np.percentile(lat, 50)), 3),
-           "serving_p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "serving_graphs": "rmat18/22/24/26, torus256, er2^23 d32 (w < log2 n); 50/50 BFS/wBFS"}
-    log(f"serving: {res}")
+           "serving_saturated": {**mix.summary(sat_records), "queries": 600,
+                                 "pool_waits": sat_waits},
+           "serving_graphs": "rmat18/22/24/26, torus256, er2^23 d32 (w < log2 n); 50/50 BFS/wBFS; "
+                             "uniform graph; 32 seeded sources per graph"}
+    for frac in (0.5, 0.8):
+        lam = frac * qps_sat
+        mix.records.clear()
+        w0 = mix.pool_waits
+        t0 = time.perf_counter()
+        tnext = t0
+        for _ in range(nq):
+            tnext += rng.exponential(1.0 / lam)
+            while time.perf_counter() < tnext:
+                mix.harvest()
+            mix.submit(*mix.draw(rng))
+        mix.finish()
+        el = time.perf_counter() - t0
+        sm = mix.summary(mix.records)
+        key = f"serving_lambda{int(frac * 10):02d}"
+        # pool_waits: arrivals that found every output pair of their graph
+        # in flight and waited for one (the arrival process then lags)
+        res[key] = {"lambda_qps": round(lam, 1), "queries": nq, "qps": round(nq / el, 1), **sm,
+                    "pool_waits": mix.pool_waits - w0}
+        log(f"serving at {frac}x ({lam:.1f} q/s offered): {nq / el:.1f} q/s, p50 {sm['p50_ms']} "
+            f"ms, p99 {sm['p99_ms']} ms")
+        for k, v in sm["per_graph_kind"].items():
+            log(f"    {k:16s} n={v['n']:4d} p50={v['p50_ms']:8.3f} p99={v['p99_ms']:8.3f} "
+                f"retried={v['retried']} packed={v['packed']}")
+    res["serving_verified_digest"] = mix.verified_digest
+    res["serving_verified_full"] = mix.verified_full
+    sv.close()
+
+    # the oracle on every host core: a seeded sample of the same mix, one
+    # query per thread
+    import oracle
+    thr = min(16, len(os.sched_getaffinity(0)))
+    r3 = np.random.default_rng(11)
+    calls = []
+    for _ in range(thr):
+        gi, kind, si = mix.draw(r3)
+        name = graphs[gi][0]
+        h, w = hosts[name]
+        s = mix.srcsets[gi][si]
+        calls.append((lambda h=h, s=s: oracle.bfs(h, s)) if kind == 0 else
+                     (lambda h=h, w=w, s=s: oracle.wbfs(h, s, weights=w)))
+    qps, wall = oracle_all_cores(calls, thr)
+    res["serving_oracle_all_cores_qps"] = round(qps, 3)
+    res["serving_oracle_all_cores_threads"] = thr
+    log(f"serving mix on the oracle, {thr} host threads: {qps:.3f} q/s ({wall:.1f} s)")
     return res
 
 

@@ -347,7 +347,14 @@ int gbgpu_bfs_multi(gbgpu_graph g, const int32_t* srcs, int32_t k,
                     int32_t* dist, int32_t* parent, const gbgpu_opts* o,
                     gbgpu_stats* st, void* stream);
 
-/* Uneven batch: nq BFS queries over several graphs in one persistent launch.
+/* Uneven batch: nq BFS queries over several graphs, answered together: the
+ * queries on each graph are packed 64 to a group (one 64-bit frontier mask
+ * per vertex and group), and one kernel launch per round advances every
+ * group of every graph (up to 64 groups per launch), each group choosing
+ * push or pull for itself; a group whose frontier is empty costs nothing.
+ * The host checks for the end after 8, 16, 32, ... launches.  Queries on
+ * graphs a single-source BFS has shown to be deeper than 64 levels run one
+ * source at a time instead.
  *   graphs   host array of nq graph handles (repeats allowed, any sizes)
  *   srcs     host int32[nq]
  *   dists    host array of nq dev int32* outputs (each n_i long)
