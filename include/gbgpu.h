@@ -201,7 +201,10 @@ int gbgpu_bfs_noalloc(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent
 
 /* Single-source integral-weight SSSP (weighted BFS problem statement; the
  * paper's wBFS algorithm box: buckets by distance, edgeMapData relaxations
- * with priority-write).
+ * with priority-write).  The first call on a graph builds a copy of every
+ * list ordered by (weight, neighbour), 6 bytes per stored edge, kept by the
+ * handle until gbgpu_graph_free (dense steps read it).  Unless o->tau is
+ * set, a bucket goes dense above m / 10.
  *   dist    dev uint32[n] output, 0xFFFFFFFF for unreachable
  *   parent  dev int32[n] output, min-ID tight parent, -1 for unreachable
  * Errors: E_INVALID (no weights, a weight below 1, bad src, null output),

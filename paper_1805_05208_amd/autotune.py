@@ -30,10 +30,21 @@ BFS_SPACE = {
     "beta": [-1, 8, 24, 64],
 }
 WBFS_SPACE = {
+    "tau": [5, 7, 10, 14, 20],
     "wave_chunk": [64, 128, 256],
     "grid": GRID_WIDE,
     "rounds_per_sync": [2, 3, 4, 8],
+    "bucket_window": [0, 128, 256],
 }
+
+
+def wbfs_space(n: int) -> Dict[str, Sequence[int]]:
+    """The weighted-BFS space for a graph of n vertices: bucket capacities
+    from n/32 to n/2 entries (0 = the library's n/4, doubled and re-run on
+    overflow), so the tuner can pick one that never overflows."""
+    sp = dict(WBFS_SPACE)
+    sp["bucket_capacity"] = [0] + [max(4096, n // d) for d in (32, 16, 8, 2)]
+    return sp
 MULTI_SPACE = {
     "tau": [5, 10, 20, 40],
     "wave_chunk": [64, 128, 256],
@@ -130,16 +141,19 @@ def tune_wbfs(G, srcs: List[int], reps: int = 2, budget_s: float = 60.0, passes:
     ref = [gb.wbfs(G, s) for s in srcs]
     _, _, st = gb.wbfs(G, srcs[0], stats=True)
     max_degree = int((G.offsets[1:] - G.offsets[:-1]).max().item())
-    start = {"wave_chunk": 256, "grid": 512, "rounds_per_sync": 3}
+    start = {"tau": 10, "wave_chunk": 256, "grid": 512, "rounds_per_sync": 3,
+             "bucket_window": 0, "bucket_capacity": 0}
 
     def cost(opts):
         for s, (d0, p0) in zip(srcs, ref):
+            # (a capacity that overflows re-runs the search, which the
+            # timing below includes)
             d, p = gb.wbfs(G, s, opts=opts)
             if not (torch.equal(d, d0) and torch.equal(p, p0)):
                 return None
         return _median_time(lambda: [gb.wbfs(G, s, opts=opts) for s in srcs], reps)
 
-    res = coordinate_descent(space or WBFS_SPACE, start, cost, passes, budget_s, verbose)
+    res = coordinate_descent(space or wbfs_space(G.n), start, cost, passes, budget_s, verbose)
     res["default_cost"] = cost(start)
     res["signature"] = signature(G.n, G.m, max_degree, st["rounds"])
     res["kind"] = "wbfs"

@@ -94,6 +94,12 @@ struct gbgpu_graph_s {
     gb::CAdj* cadj = nullptr;    // compressed copy of the lists and its BFS workspace
     gb::WbfsWs* wbfs = nullptr;
     gb::MultiWs* multi = nullptr;
+    // owned, built on the first weighted BFS: every list re-ordered by
+    // (weight, neighbour), neighbours and 16-bit weights (dense weighted
+    // steps stop at the first in-bucket neighbour in that order)
+    uint32_t* wsort_nbr = nullptr;
+    uint16_t* wsort_w = nullptr;
+    std::mutex wsort_mu;
 };
 
 namespace gb {
@@ -111,6 +117,9 @@ void free_multi_ws(MultiWs* w);
 double now_ms();
 int64_t now_ns();
 gbgpu_opts resolve_opts(const gbgpu_opts* o);
+// Index of the reserved option word resolve_opts sets to 1 when the caller
+// left tau at 0 (the library's default).
+constexpr int kTauDefaulted = 0;
 int ensure_pull_plan(gbgpu_graph g);
 constexpr uint32_t kPlanCap = 1024;   // max edges of one dense-scan work item
 constexpr uint32_t kPlanHub = 0xFFFFFFFFu;

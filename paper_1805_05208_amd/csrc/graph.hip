@@ -121,6 +121,9 @@ gbgpu_opts resolve_opts(const gbgpu_opts* o) {
     memset(&r, 0, sizeof(r));
     if (o) r = *o;
     if (r.force_direction < 0 || r.force_direction > 3) r.force_direction = 0;
+    // reserved[kTauDefaulted] tells the traversals that pick their own
+    // threshold (weighted BFS) that the caller left tau unset
+    r.reserved[kTauDefaulted] = r.tau <= 0 ? 1 : 0;
     if (r.tau <= 0) r.tau = 20;
     if (r.pull_light <= 0) r.pull_light = 32;
     if (r.wave_chunk <= 0) r.wave_chunk = 256;
@@ -506,6 +509,8 @@ int gbgpu_graph_free(gbgpu_graph g) {
         if (g->core) (void)hipFree(g->core);
         if (g->core_head) (void)hipFree(g->core_head);
         if (g->leaf) (void)hipFree(g->leaf);
+        if (g->wsort_nbr) (void)hipFree(g->wsort_nbr);
+        if (g->wsort_w) (void)hipFree(g->wsort_w);
         (void)hipFree(g->deg);
         (void)hipFree(g->pruned);
         (void)hipFree(g->head);

@@ -35,11 +35,16 @@
 //   dense    edgeMapData's dense form for a heavy bucket (entries + their
 //            degrees > m / tau): the launch that finds b only marks b's live
 //            vertices in a bucket bitmap (and the settled bitmap); the next
-//            launch pulls: every unsettled vertex v scans its whole list and
-//            takes min over u in bucket b of ((b + w(u,v)) << 32 | u), which is
-//            the same value the pushes of bucket b would leave in key[v].  The
-//            handover between the two launches goes through control words on
-//            the device, so the host still launches blindly.
+//            launch pulls: every unsettled vertex v takes min over u in bucket
+//            b of ((b + w(u,v)) << 32 | u), which is the same value the pushes
+//            of bucket b would leave in key[v].  The pull reads a copy of each
+//            list ordered by (weight, neighbour), built once per graph, so the
+//            first in-bucket neighbour in that order is the minimum and the
+//            scan stops there, or at the first weight too large to lower
+//            key[v].  The handover between the two launches goes through
+//            control words on the device, so the host still launches blindly.
+
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "common.h"
 #include "emit.h"
@@ -47,6 +52,7 @@
 namespace gb {
 
 constexpr int kWLogCap = 16384;
+constexpr int kWbfsTau = 10;  // default dense threshold m / 10 (see run_wbfs_ws)
 constexpr uint32_t kStart = 0xFFFFFFFFu;  // "bucket before 0"
 constexpr uint32_t kDone = 0xFFFFFFFEu;
 
@@ -147,10 +153,70 @@ static int ensure_wbfs_ws(gbgpu_graph g, uint32_t NB, uint32_t C) {
     return GBGPU_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Lists ordered by (weight, neighbour), for the dense steps: a stable
+// segmented radix sort of each list (already ascending by neighbour) by its
+// 11-bit weights.  Built once per graph by the first weighted BFS; 6 bytes
+// per stored edge.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void wsort_keys_kernel(const int32_t* wt, int64_t m,
+                                                           uint16_t* k) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < m; i += stride) k[i] = (uint16_t)wt[i];
+}
+
+static int ensure_wsort(gbgpu_graph g, hipStream_t stream) {
+    std::lock_guard<std::mutex> lk(g->wsort_mu);
+    if (g->wsort_nbr) return GBGPU_OK;
+    const size_t m = (size_t)std::max<int64_t>(g->m, 1);
+    uint16_t* kin = nullptr;
+    uint16_t* kout = nullptr;
+    uint32_t* vout = nullptr;
+    void* tmp = nullptr;
+    auto fail = [&](int st) {
+        if (kin) (void)hipFree(kin);
+        if (kout) (void)hipFree(kout);
+        if (vout) (void)hipFree(vout);
+        if (tmp) (void)hipFree(tmp);
+        return st;
+    };
+    if (hipMalloc(&kin, m * 2) != hipSuccess || hipMalloc(&kout, m * 2) != hipSuccess ||
+        hipMalloc(&vout, m * 4) != hipSuccess)
+        return fail(set_error(GBGPU_E_NOMEM, "weight-ordered lists: %zu bytes", m * 8));
+    if (g->m > 0) {
+        const int grid = (int)std::min<int64_t>((g->m + kBlock - 1) / kBlock, 8192);
+        hipLaunchKernelGGL(wsort_keys_kernel, dim3(grid), dim3(kBlock), 0, stream, g->w, g->m,
+                           kin);
+        if (hipGetLastError() != hipSuccess)
+            return fail(set_error(GBGPU_E_HIP, "weight key kernel failed"));
+        const uint32_t* vin = reinterpret_cast<const uint32_t*>(g->nbr);
+        size_t tb = 0;
+        if (rocprim::segmented_radix_sort_pairs(nullptr, tb, kin, kout, vin, vout,
+                                                (unsigned int)g->m, (unsigned int)g->n, g->off,
+                                                g->off + 1, 0u, 11u, stream) != hipSuccess)
+            return fail(set_error(GBGPU_E_HIP, "weight-ordered lists: sort sizing failed"));
+        if (hipMalloc(&tmp, std::max<size_t>(tb, 1)) != hipSuccess)
+            return fail(set_error(GBGPU_E_NOMEM, "weight-ordered lists: sort storage"));
+        if (rocprim::segmented_radix_sort_pairs(tmp, tb, kin, kout, vin, vout,
+                                                (unsigned int)g->m, (unsigned int)g->n, g->off,
+                                                g->off + 1, 0u, 11u, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return fail(set_error(GBGPU_E_HIP, "weight-ordered lists: sort failed"));
+    }
+    (void)hipFree(kin);
+    if (tmp) (void)hipFree(tmp);
+    g->wsort_w = kout;
+    g->wsort_nbr = vout;
+    return GBGPU_OK;
+}
+
 struct WbfsArgs {
     const int64_t* off;
     const int32_t* nbr;
     const int32_t* wt;
+    const uint32_t* snbr;    // lists ordered by (weight, neighbour): neighbours
+    const uint16_t* sw;      // ... and their weights
     const uint32_t* deg;
     unsigned long long* key;
     uint32_t* Qs;
@@ -454,6 +520,18 @@ constexpr int kPullWin = 2;  // 64-edge windows whose loads are issued together
 // One dense-scan work item: a run of at most 64 consecutive vertices whose
 // lists hold at most 1024 edges together, or a piece of at most 1024 edges of
 // one high-degree vertex.  Settled vertices are skipped.  Wave-uniform.
+//
+// The lists are read in (weight, neighbour) order.  A candidate from an
+// in-bucket neighbour u is ((b + w(u,v)) << 32 | u), so in that order the
+// first in-bucket neighbour gives the minimum and the scan of v ends there;
+// it also ends at the first weight above room = d(v) - b, the largest weight
+// that can still lower key[v] (an equal distance can still bring a smaller
+// parent).
+// A run's per-vertex minimum slot holds ~0 (scan going on, nothing found),
+// a candidate key, or kScanEnded (ended by a heavy edge without a candidate;
+// every real key is smaller, since distances stay below 2^32 - 2).
+constexpr unsigned long long kScanEnded = ~0ull - 1ull;
+
 __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t* F, uint32_t b,
                                                uint4 it, unsigned long long* smin,
                                                WgBuckets& q) {
@@ -462,14 +540,21 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
     uint32_t v = 0, nd = 0;
     if (it.z == kPlanHub) {
         v = it.x + (uint32_t)l;
-        bool valid = v < it.y && !test_bit(a.S, v);
-        const uint32_t dg = valid ? a.deg[v] : 0u;
-        valid = valid && dg > 0u;
+        // the settled bit, degree, list start and key are loaded together
+        // (one trip; the run's vertices are consecutive, so each load is
+        // coalesced) and only then tested
+        const bool inr = v < it.y;
+        const uint32_t sword = inr ? a.S[v >> 5] : ~0u;
+        const uint32_t dg = inr ? a.deg[v] : 0u;
+        const int64_t st0 = inr ? a.off[v] : 0;
+        const unsigned long long old0 = inr ? a.key[v] : 0ull;
+        const bool valid = inr && !((sword >> (v & 31)) & 1u) && dg > 0u;
         if (!ballot(valid)) return;
-        const int64_t st = valid ? a.off[v] : 0;
-        const unsigned long long old = valid ? a.key[v] : 0ull;
-        // unsettled, so its tentative distance is above b
-        const uint32_t room = valid ? (uint32_t)(old >> 32) - b : 0u;
+        const int64_t st = valid ? st0 : 0;
+        const unsigned long long old = valid ? old0 : 0ull;
+        // unsettled, so its tentative distance is above b; room 0 marks a
+        // vertex whose scan has ended
+        uint32_t room = valid ? (uint32_t)(old >> 32) - b : 0u;
         smin[l] = ~0ull;
         wave_lds_sync();
         // the run's lists, concatenated, walked kPullWin x 64 edges at a time:
@@ -479,8 +564,9 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
         const uint32_t T = __shfl(inc, 63, 64);
         const uint32_t myP = inc - d;  // lanes without edges share the next lane's prefix
         for (uint32_t e0 = 0; e0 < T; e0 += kPullWin * kWave) {
+            if (!ballot(room != 0u)) break;  // every scan of the run has ended
             // (edge indices fit in 32 bits)
-            uint32_t wk[kPullWin], uk[kPullWin], ok[kPullWin], ek[kPullWin];
+            uint32_t wk[kPullWin], uk[kPullWin], ok[kPullWin], ek[kPullWin], rk[kPullWin];
 #pragma unroll
             for (int k = 0; k < kPullWin; ++k) {
                 const uint32_t t = e0 + 64u * k + (uint32_t)l;
@@ -492,23 +578,28 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
                 }
                 ok[k] = (uint32_t)o;
                 ek[k] = __shfl((uint32_t)st, o, 64) + (t - __shfl(myP, o, 64));
-                wk[k] = t < T ? (uint32_t)a.wt[ek[k]] : 0u;
+                rk[k] = __shfl(room, o, 64);
+                wk[k] = (t < T && rk[k] != 0u) ? (uint32_t)a.sw[ek[k]] : 0u;
             }
 #pragma unroll
             for (int k = 0; k < kPullWin; ++k) {
-                const uint32_t t = e0 + 64u * k + (uint32_t)l;
-                const uint32_t room_o = __shfl(room, (int)ok[k], 64);
-                uk[k] = (t < T && wk[k] <= room_o) ? (uint32_t)a.nbr[ek[k]] : kNone;
+                const bool light = wk[k] != 0u && wk[k] <= rk[k];
+                uk[k] = light ? a.snbr[ek[k]] : kNone;
+                // a heavier edge ends the scan: the rest of the list is heavier
+                if (wk[k] > rk[k]) atomicMin(&smin[ok[k]], kScanEnded);
             }
 #pragma unroll
             for (int k = 0; k < kPullWin; ++k) {
                 if (uk[k] != kNone && test_bit(F, uk[k]))
                     atomicMin(&smin[ok[k]], ((unsigned long long)(b + wk[k]) << 32) | uk[k]);
             }
+            wave_lds_sync();
+            // a hit ends the scan too: everything after it is a larger key
+            if (smin[l] != ~0ull) room = 0u;
         }
         wave_lds_sync();
         const unsigned long long best = smin[l];
-        if (valid && best != ~0ull) {
+        if (valid && best < kScanEnded) {
             if (best < old) {
                 a.key[v] = best;  // the run owns v: no other writer this step
                 nd = (uint32_t)(best >> 32);
@@ -517,20 +608,26 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
         }
     } else {
         v = it.x;
-        if (test_bit(a.S, v)) return;
-        const uint32_t room = (uint32_t)(a.key[v] >> 32) - b;
+        const uint32_t sword = a.S[v >> 5];
+        const unsigned long long old0 = a.key[v];
+        if ((sword >> (v & 31)) & 1u) return;
+        // one piece of a long list, in (weight, neighbour) order; pieces of
+        // one list run independently and meet in the atomic minimum
+        const uint32_t room = (uint32_t)(old0 >> 32) - b;
         unsigned long long best = ~0ull;
         for (uint32_t e0 = it.z; e0 < it.w; e0 += kPullWin * kWave) {
             uint32_t wk[kPullWin], uk[kPullWin];
 #pragma unroll
             for (int k = 0; k < kPullWin; ++k) {
                 const uint32_t e = e0 + 64u * k + (uint32_t)l;
-                wk[k] = e < it.w ? (uint32_t)a.wt[e] : 0u;
+                wk[k] = e < it.w ? (uint32_t)a.sw[e] : 0u;
             }
+            bool heavy = false;
 #pragma unroll
             for (int k = 0; k < kPullWin; ++k) {
-                const uint32_t e = e0 + 64u * k + (uint32_t)l;
-                uk[k] = (e < it.w && wk[k] <= room) ? (uint32_t)a.nbr[e] : kNone;
+                const bool light = wk[k] != 0u && wk[k] <= room;
+                heavy |= wk[k] > room;
+                uk[k] = light ? a.snbr[e0 + 64u * k + (uint32_t)l] : kNone;
             }
 #pragma unroll
             for (int k = 0; k < kPullWin; ++k) {
@@ -539,11 +636,12 @@ __device__ __forceinline__ void wbfs_pull_item(const WbfsArgs& a, const uint32_t
                     best = c < best ? c : best;
                 }
             }
-        }
 #pragma unroll
-        for (int s = 32; s >= 1; s >>= 1) {
-            const unsigned long long o = shfl64(best, l ^ s);
-            best = o < best ? o : best;
+            for (int s = 32; s >= 1; s >>= 1) {
+                const unsigned long long o = shfl64(best, l ^ s);
+                best = o < best ? o : best;
+            }
+            if (best != ~0ull || ballot(heavy)) break;
         }
         if (l == 0 && best != ~0ull && best < a.key[v]) {
             // several pieces of v may race: atomicMin, and a move only on a
@@ -706,10 +804,13 @@ __global__ __launch_bounds__(kBlock) void wbfs_finalize_kernel(const unsigned lo
 int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* parent,
                 const gbgpu_opts& o, gbgpu_stats* st, hipStream_t stream, bool* overflow) {
     const double t0 = now_ms();
+    GB_TRY(ensure_wsort(g, stream));
     WbfsArgs a;
     a.off = g->off;
     a.nbr = g->nbr;
     a.wt = g->w;
+    a.snbr = g->wsort_nbr;
+    a.sw = g->wsort_w;
     a.deg = g->deg;
     a.key = w->key;
     a.Qs = w->Qs;
@@ -730,7 +831,13 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
     a.nplan = g->nplan;
     a.dense_mode = (uint32_t)(o.force_direction == 1 ? 1 : o.force_direction == 2 ? 2
                               : o.force_direction == 3 ? 3 : 0);
-    a.dense_thresh = (unsigned long long)g->m / (unsigned long long)std::max(o.tau, 1);
+    // a bucket goes dense when its entries + their degrees exceed m / tau;
+    // unless the caller sets tau, 10 (RMAT scale 24, w < 24: 7.3 ms per
+    // source against 8.2 at 20 and 7.9 at 5; the dense steps cannot stop
+    // at the first frontier neighbour the way BFS's do, so they pay off
+    // only for heavier buckets)
+    const int tau = o.reserved[kTauDefaulted] ? kWbfsTau : std::max(o.tau, 1);
+    a.dense_thresh = (unsigned long long)g->m / (unsigned long long)tau;
     const int igrid = (int)std::min<int64_t>(std::max<int64_t>((g->n + kBlock - 1) / kBlock, 64), 4096);
     hipLaunchKernelGGL(wbfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a, (uint32_t)src);
     GB_HIP(hipGetLastError());
