@@ -159,15 +159,17 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
         const int nv = (int)min<int64_t>(64, G.n - v0);
         __syncthreads();
         if (t < nv) tv[t] = G.VM[v0 + t];
+        __syncthreads();
         const int j = t & 63;
         // all of this thread's loads are issued before any LDS store, so each
-        // thread keeps 32 reads in flight
+        // thread keeps 32 reads in flight; pairs the search never reached are
+        // not read (their row entries are written as unreachable below)
         constexpr int kRows = 64 / (kBlock / 64);
         uint32_t lp[kRows], ld[kRows];
 #pragma unroll
         for (int i = 0; i < kRows; ++i) {
             const int vi = (t >> 6) + i * (kBlock / 64);
-            const bool ok = vi < nv && j < k;
+            const bool ok = vi < nv && j < k && ((tv[vi < nv ? vi : 0] >> j) & 1ull);
             lp[i] = ok ? G.PS[(size_t)(v0 + vi) * k + j] : 0u;
             ld[i] = ok ? G.DS[(size_t)(v0 + vi) * k + j] : 0u;
         }

@@ -62,3 +62,27 @@ def test_server_arena_allocator_selftest(libpath):
     L = gb.lib()
     for seed in range(1, 6):
         assert L.gbgpu_debug_arena_selftest(seed, 4000) == gb.OK, L.gbgpu_last_error()
+
+
+def test_load_limits_refused_before_device_work(libpath):
+    """Sizes beyond the library's limits are refused by argument checks that
+    run before any device call (so this runs on the CPU): n >= 2^31 - 1 and
+    m >= 2^31 give E_UNSUPPORTED, a missing SYMMETRIC flag or a NULL array
+    E_INVALID.  The pointers passed are never dereferenced."""
+    import paper_1805_05208_amd as gb
+    L = gb.lib()
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never read: the size checks come first
+    assert L.gbgpu_load_csr(2**31 - 1, 10, fake, fake, None, gb.SYMMETRIC, None,
+                            ctypes.byref(out)) == gb.E_UNSUPPORTED
+    assert b"2^31" in L.gbgpu_last_error()
+    assert L.gbgpu_load_csr(100, 2**31, fake, fake, None, gb.SYMMETRIC, None,
+                            ctypes.byref(out)) == gb.E_UNSUPPORTED
+    assert b"2^31 - 1" in L.gbgpu_last_error()
+    assert L.gbgpu_load_csr(100, 10, fake, fake, None, 0, None,
+                            ctypes.byref(out)) == gb.E_INVALID
+    assert L.gbgpu_load_csr(100, 10, None, fake, None, gb.SYMMETRIC, None,
+                            ctypes.byref(out)) == gb.E_INVALID
+    assert L.gbgpu_load_csr(0, 0, fake, fake, None, gb.SYMMETRIC, None,
+                            ctypes.byref(out)) == gb.E_INVALID
+    assert out.value is None
