@@ -841,7 +841,7 @@ class ServedMix:
                     assert self.torch.equal(d, rd) and self.torch.equal(p, rp)
                     self.verified_full += 1
                 self.records.append((gi, kind, (r["t_done_ns"] - r["t_arrive_ns"]) / 1e6,
-                                     r["retries"], r["batch"]))
+                                     r["retries"], r["batch"], r["join_round"]))
                 self.free[gi].append(b)
             if done or not block or not self.out:
                 return
@@ -871,7 +871,8 @@ class ServedMix:
                     "n": len(sel), "p50_ms": round(float(np.percentile(l, 50)), 3),
                     "p99_ms": round(float(np.percentile(l, 99)), 3),
                     "retried": int(sum(1 for r in sel if r[3] > 0)),
-                    "packed": int(sum(1 for r in sel if r[4] > 1))}
+                    "packed": int(sum(1 for r in sel if r[4] > 1)),
+                    "joined": int(sum(1 for r in sel if r[5] > 0))}
         out["per_graph_kind"] = per
         return out
 
@@ -962,7 +963,7 @@ def run_serving(g, G, gg, gb, torch, nq=2000):
             f"ms, p99 {sm['p99_ms']} ms")
         for k, v in sm["per_graph_kind"].items():
             log(f"    {k:16s} n={v['n']:4d} p50={v['p50_ms']:8.3f} p99={v['p99_ms']:8.3f} "
-                f"retried={v['retried']} packed={v['packed']}")
+                f"retried={v['retried']} packed={v['packed']} joined={v['joined']}")
     res["serving_verified_digest"] = mix.verified_digest
     res["serving_verified_full"] = mix.verified_full
     sv.close()

@@ -395,7 +395,12 @@ typedef struct {
     int32_t retries;     /* weighted BFS: runs repeated after a bucket
                             overflow (each doubles the bucket capacity)    */
     int32_t batch;       /* queries in the run that answered this one (1,
-                            or the size of a bit-packed same-graph group)  */
+                            or the size of a bit-packed same-graph group,
+                            including queries that joined it)             */
+    int32_t join_round;  /* BFS that joined a running packed group: the
+                            group's round it joined before (0 otherwise);
+                            t_start_ns is then the time it joined          */
+    int32_t reserved;
 } gbgpu_result;
 
 /* Create a server.
@@ -449,6 +454,17 @@ int gbgpu_debug_bfs_log(gbgpu_graph g, uint32_t* out, int32_t max_rounds, int32_
  * 1 marks the bucket's vertices, 2 pulls).  out holds max_steps * 4 words
  * (host). */
 int gbgpu_debug_wbfs_log(gbgpu_graph g, uint32_t* out, int32_t max_steps, int32_t* nsteps);
+
+/* Round-boundary admission (as the server's packed BFS groups use it):
+ * runs srcs[0 .. k0) as one bit-packed group with room for 64 sources and,
+ * at the first round boundary the host sees (every 4 rounds) at or after
+ * round join_round -- or earlier, if the group runs out of work first --
+ * adds srcs[k0 .. k0+k1) to it.  Row i of dist / parent (dev int32, stride
+ * n) is the BFS from srcs[i] (host int32[k0 + k1]), the same as gbgpu_bfs
+ * from it.  k0 >= 1, k0 + k1 <= 64.  Allocates its workspace per call;
+ * returns when the rows are complete. */
+int gbgpu_debug_bfs_join(gbgpu_graph g, const int32_t* srcs, int32_t k0, int32_t k1,
+                         int32_t join_round, int32_t* dist, int32_t* parent, void* stream);
 
 /* Host-only randomized self-test of the server's first-fit arena allocator
  * (no device work); GBGPU_OK when every allocation matched a reference. */

@@ -34,6 +34,7 @@ EXPORTED = [
     "gbgpu_server_create", "gbgpu_server_add_graph", "gbgpu_submit", "gbgpu_poll",
     "gbgpu_server_drain", "gbgpu_server_destroy", "gbgpu_query_footprint",
     "gbgpu_debug_bfs_log", "gbgpu_debug_wbfs_log", "gbgpu_debug_arena_selftest",
+    "gbgpu_debug_bfs_join",
 ]
 
 
@@ -79,6 +80,7 @@ class Result(ctypes.Structure):
         ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
         ("t_arrive_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
         ("t_done_ns", ctypes.c_int64), ("retries", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("join_round", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -125,6 +127,7 @@ def lib() -> ctypes.CDLL:
             "gbgpu_debug_bfs_log": ([P, P, I32, P], ctypes.c_int),
             "gbgpu_debug_wbfs_log": ([P, P, I32, P], ctypes.c_int),
             "gbgpu_debug_arena_selftest": ([U64, I32], ctypes.c_int),
+            "gbgpu_debug_bfs_join": ([P, P, I32, I32, I32, P, P, P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -395,6 +398,21 @@ def bfs_multi(g: Graph, srcs: Sequence[int], dist=None, parent=None, opts=None, 
     return (dist, parent, st.as_dict()) if stats else (dist, parent)
 
 
+def bfs_join(g: Graph, srcs: Sequence[int], k0: int, join_round: int, stream=None):
+    """Diagnostic of round-boundary admission: srcs[:k0] start a packed
+    group, srcs[k0:] join it at the first round boundary >= join_round.
+    Returns (dist, parent) of shape [len(srcs), n]."""
+    s = np.ascontiguousarray(np.asarray(srcs, dtype=np.int32))
+    k = int(s.size)
+    dist = torch.empty((k, g.n), dtype=torch.int32, device="cuda")
+    parent = torch.empty((k, g.n), dtype=torch.int32, device="cuda")
+    _check(lib().gbgpu_debug_bfs_join(g.handle, ctypes.c_void_p(s.ctypes.data), int(k0),
+                                      k - int(k0), int(join_round),
+                                      ctypes.c_void_p(dist.data_ptr()),
+                                      ctypes.c_void_p(parent.data_ptr()), _stream_ptr(stream)))
+    return dist, parent
+
+
 def bfs_batch(graphs: Sequence[Graph], srcs: Sequence[int], dists=None, parents=None,
               opts=None, stream=None, stats: bool = False):
     """Uneven batch of BFS queries over several graphs in one launch.
@@ -471,7 +489,7 @@ class Server:
         _check(st)
         return {"status": r.status, "rounds": r.rounds, "t_arrive_ns": r.t_arrive_ns,
                 "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns, "retries": r.retries,
-                "batch": r.batch}
+                "batch": r.batch, "join_round": r.join_round}
 
     def drain(self):
         _check(lib().gbgpu_server_drain(self.handle))

@@ -69,8 +69,10 @@ struct PendingQ {
     uint64_t ticket;
     gbgpu_query q;
     int64_t t_arrive;
-    uint32_t cap;     // weighted BFS bucket capacity override (0 = default)
-    int32_t retries;  // runs repeated after a bucket overflow
+    uint32_t cap;        // weighted BFS bucket capacity override (0 = default)
+    int32_t retries;     // runs repeated after a bucket overflow
+    int64_t t_start;     // when it joined a running group (0: with the run)
+    int32_t join_round;  // round of the running group it joined before
 };
 
 // Largest graph whose same-graph BFS queries are bit-packed together, and
@@ -90,19 +92,36 @@ struct SchedEnv {
     std::function<size_t(int32_t gid, int64_t k)> packed_bytes;
 };
 
+// Takes the first k pending BFS queries on graph gid (in their order).
+inline void sched_take_bfs(std::deque<PendingQ>& pending, int32_t gid, int k,
+                           std::vector<PendingQ>* out) {
+    for (auto it = pending.begin(); it != pending.end() && (int)out->size() < k;) {
+        if (it->q.kind == GBGPU_QUERY_BFS && it->q.graph_id == gid) {
+            out->push_back(*it);
+            it = pending.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
 // Admission: looks at the oldest pending query.  A BFS on a packable graph
 // takes, with it, the other pending BFS queries on the same graph (oldest
-// first, up to kPackedMaxK) as the largest group whose workspace fits,
-// halving the group size from all of them down to 2; otherwise the oldest
-// query runs alone if its footprint fits (a weighted query with the bucket
-// capacity an earlier query on its graph grew to, from learned_cap);
-// otherwise nothing is taken and the worker waits for memory (later queries
-// do not overtake the oldest).  On success the taken queries leave `pending`
-// in their order, `off`/`bytes` hold the workspace in the arena.
+// first, up to kPackedMaxK): as a group with room for kPackedMaxK sources
+// when that workspace fits (*kcap = kPackedMaxK: later BFS arrivals on the
+// graph may join it at a round boundary), else as the largest group whose
+// workspace fits, halving the group size from all of them down to 2
+// (*kcap = its size); otherwise the oldest query runs alone if its
+// footprint fits (a weighted query with the bucket capacity an earlier
+// query on its graph grew to, from learned_cap; *kcap = 0); otherwise
+// nothing is taken and the worker waits for memory (later queries do not
+// overtake the oldest).  On success the taken queries leave `pending` in
+// their order, `off`/`bytes` hold the workspace in the arena.
 inline bool sched_admit(std::deque<PendingQ>& pending, ArenaAlloc& alloc, const SchedEnv& env,
                         const std::vector<uint32_t>& learned_cap, std::vector<PendingQ>* job,
-                        size_t* off, size_t* bytes) {
+                        size_t* off, size_t* bytes, uint32_t* kcap) {
     job->clear();
+    *kcap = 0;
     if (pending.empty()) return false;
     const PendingQ& head = pending.front();
     const int32_t gid = head.q.graph_id;
@@ -110,18 +129,21 @@ inline bool sched_admit(std::deque<PendingQ>& pending, ArenaAlloc& alloc, const 
     if (head.q.kind == GBGPU_QUERY_BFS && env.packable(gid))
         for (auto& p : pending)
             if (p.q.kind == GBGPU_QUERY_BFS && p.q.graph_id == gid && nsame < kPackedMaxK) ++nsame;
+    if (nsame > 1) {
+        const size_t bb = env.packed_bytes(gid, kPackedMaxK);
+        if (alloc.alloc(bb, off)) {
+            *bytes = bb;
+            *kcap = kPackedMaxK;
+            sched_take_bfs(pending, gid, nsame, job);
+            return true;
+        }
+    }
     for (int kb = nsame; kb > 1; kb /= 2) {
         const size_t bb = env.packed_bytes(gid, kb);
         if (alloc.alloc(bb, off)) {
             *bytes = bb;
-            for (auto it = pending.begin(); it != pending.end() && (int)job->size() < kb;) {
-                if (it->q.kind == GBGPU_QUERY_BFS && it->q.graph_id == gid) {
-                    job->push_back(*it);
-                    it = pending.erase(it);
-                } else {
-                    ++it;
-                }
-            }
+            *kcap = (uint32_t)kb;
+            sched_take_bfs(pending, gid, kb, job);
             return true;
         }
     }

@@ -111,6 +111,13 @@ struct MsQuery {
     int32_t* parent;
 };
 
+// Round-boundary admission into a running single-group batch: called with
+// the next round r, the number of free source slots and whether the group
+// has run out of work (it ends unless someone joins); appends the queries
+// that join the group before round r.
+using MsJoinHook =
+    std::function<void(uint32_t r, int room, bool idle, std::vector<MsQuery>* add)>;
+
 void free_bfs_ws(BfsWs* w);
 void free_wbfs_ws(WbfsWs* w);
 void free_multi_ws(MultiWs* w);

@@ -37,7 +37,7 @@ struct MsGroupDev {
     const uint32_t* deg;
     int64_t n;
     uint64_t dense_thresh;
-    unsigned long long kmask;   // bits of the sources in this group
+    unsigned long long kmask;   // bits of the sources in this group (kused of them)
     unsigned long long* VM;     // n
     unsigned long long* F[3];   // n each
     uint32_t* Q[2];             // n + 64 each
@@ -47,9 +47,11 @@ struct MsGroupDev {
     int32_t* const* prow;       // 64 row pointers (parent), device array
     const uint4* plan;          // dense-scan work items of the graph
     uint32_t nplan;
-    uint32_t k;                 // sources in the group
+    uint32_t k;                 // capacity: sources the staging holds per vertex
+    uint32_t kused;             // sources in the group so far (bits 0 .. kused-1)
     uint32_t* PS;               // vertex-major parents, PS[v * k + j]
-    uint32_t* DS;               // vertex-major distances, DS[v * k + j]
+    uint32_t* DS;               // vertex-major rounds of arrival, DS[v * k + j]
+    uint32_t* start;            // round at which source j joined the group (64)
 };
 
 struct MsArgs {
@@ -132,26 +134,88 @@ __global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* s
         G.PS[(size_t)s * G.k + j] = s;
         G.DS[(size_t)s * G.k + j] = 0;
     }
+    for (int j = 0; j < 64; ++j) G.start[j] = 0;
     G.ctl[0] = ((unsigned long long)cnt << 32) | edges;  // qcnt slot 0
     ms_tot(G, 0)[0] = ((unsigned long long)cnt << 32) | edges;
 }
 
+// Before sources join a group whose frontier ran empty: the rounds since
+// then skipped their frontier bookkeeping, so one of the three frontier
+// arrays may still hold the last non-empty frontier.
+__global__ __launch_bounds__(kBlock) void ms_clear_frontiers_kernel(MsGroupDev* groups, int32_t gi) {
+    const MsGroupDev G = groups[gi];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = tid; v < G.n; v += stride) {
+        G.F[0][v] = 0ull;
+        G.F[1][v] = 0ull;
+        G.F[2][v] = 0ull;
+    }
+}
+
+// Round-boundary admission: sources j0 .. j0+cnt-1 join a running group
+// before round r (the stream is idle between rounds r-1 and r).  Each new
+// source enters round r's frontier (and its list, when the group keeps
+// one) exactly as a source enters round 0, and its rounds are counted from
+// r: row j's distance is the round of arrival minus start[j].  A group
+// whose frontier was empty gets a fresh (valid) list.
+__global__ void ms_join_kernel(MsGroupDev* groups, int32_t gi, uint32_t r, const uint32_t* srcs,
+                               uint32_t j0, uint32_t cnt) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    MsGroupDev& G = groups[gi];
+    unsigned long long* F = G.F[r % 3];
+    unsigned long long* tot = ms_tot(G, r);
+    unsigned long long t = 0;
+    for (int c = 0; c < kSpread; ++c) t += tot[(size_t)c * kSpreadStride];
+    if ((t >> 32) == 0) G.ctl[4 + (r & 3u)] = 0ull;
+    const bool qvalid = G.ctl[4 + (r & 3u)] == 0ull;
+    uint32_t qn = (uint32_t)(t >> 32), edges = (uint32_t)t;
+    unsigned long long add = 0, bits = 0;
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t s = srcs[i];
+        const uint32_t j = j0 + i;
+        if (F[s] == 0ull) {
+            if (qvalid) {
+                G.Q[r & 1u][qn] = s;
+                G.P[r & 1u][qn] = edges;
+            }
+            ++qn;
+            edges += G.deg[s];
+            add += (1ull << 32) | G.deg[s];
+        }
+        F[s] |= 1ull << j;
+        G.VM[s] |= 1ull << j;
+        G.PS[(size_t)s * G.k + j] = s;
+        G.DS[(size_t)s * G.k + j] = r;
+        G.start[j] = r;
+        bits |= 1ull << j;
+    }
+    tot[0] += add;
+    if (qvalid) G.ctl[r & 3u] += add;
+    G.kmask |= bits;
+    G.kused = j0 + cnt;
+}
+
 // Final layout: row j of the caller's output = source j.  Each workgroup
-// moves a tile of 64 vertices x k sources through LDS so both the
+// moves a tile of 64 vertices x kused sources through LDS so both the
 // vertex-major reads and the row writes are coalesced; unreached pairs get
-// (INT32_MAX, -1).
+// (INT32_MAX, -1); a distance is the round of arrival minus the round the
+// source joined (0 unless it joined a running group).
 __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups, int32_t gi) {
     __shared__ uint32_t tp[64][65];
     __shared__ uint32_t td[64][65];
     __shared__ unsigned long long tv[64];
     __shared__ int32_t* rd[64];
     __shared__ int32_t* rp[64];
+    __shared__ uint32_t st[64];
     const MsGroupDev G = groups[gi];
-    const int k = (int)G.k;
+    const int k = (int)G.k;       // staging stride
+    const int ku = (int)G.kused;  // rows to write
     const int t = threadIdx.x;
-    if (t < k) {
+    if (t < ku) {
         rd[t] = G.drow[t];
         rp[t] = G.prow[t];
+        st[t] = G.start[t];
     }
     // thread t handles source column (t % 64) in the load phase and writes
     // four consecutive vertices of row (t / 16 + 16 * pass) in the store phase
@@ -169,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
 #pragma unroll
         for (int i = 0; i < kRows; ++i) {
             const int vi = (t >> 6) + i * (kBlock / 64);
-            const bool ok = vi < nv && j < k && ((tv[vi < nv ? vi : 0] >> j) & 1ull);
+            const bool ok = vi < nv && j < ku && ((tv[vi < nv ? vi : 0] >> j) & 1ull);
             lp[i] = ok ? G.PS[(size_t)(v0 + vi) * k + j] : 0u;
             ld[i] = ok ? G.DS[(size_t)(v0 + vi) * k + j] : 0u;
         }
@@ -181,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
         }
         __syncthreads();
         const int q = t & 15;  // four vertices 4q .. 4q+3
-        for (int row = t >> 4; row < k; row += kBlock / 16) {
+        for (int row = t >> 4; row < ku; row += kBlock / 16) {
             const int vb = 4 * q;
             if (vb >= nv) continue;
             int32_t dv[4], pv[4];
@@ -189,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
             for (int i = 0; i < 4; ++i) {
                 const int vi = vb + i;
                 const bool reached = vi < nv && ((tv[vi < nv ? vi : 0] >> row) & 1ull);
-                dv[i] = reached ? (int32_t)td[vi][row] : INT32_MAX;
+                dv[i] = reached ? (int32_t)(td[vi][row] - st[row]) : INT32_MAX;
                 pv[i] = reached ? (int32_t)tp[vi][row] : -1;
             }
             int32_t* drow = rd[row] + v0 + vb;
@@ -640,9 +704,15 @@ size_t ms_pin_bytes() { return (size_t)kMaxGroups * kSpread * kSpreadStride * 8;
 // Runs groups[g0 .. g0+NG) in one launch per round, with `mem` holding
 // ms_chunk_bytes() bytes of device memory and `pin` ms_pin_bytes() of pinned
 // host memory.
+// With a join hook (one group only) the group's staging holds kcap sources
+// and the hook is asked at every round boundary the host sees (every 4
+// launches) for queries to add: up to kcap - kused of them join before the
+// next round.
 static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::vector<int>>& groups,
                         size_t gb0, int NG, void* mem, void* pin, const gbgpu_opts& o,
-                        hipStream_t stream, int* rounds_out, int* launches_out) {
+                        hipStream_t stream, int* rounds_out, int* launches_out,
+                        uint32_t kcap = 0, const MsJoinHook* hook = nullptr) {
+    const bool joinable = hook != nullptr && NG == 1;
     char* p = (char*)mem;
     MsGroupDev* dgroups = (MsGroupDev*)p; p += al256(sizeof(MsGroupDev) * NG);
     uint32_t* dsrcs = (uint32_t*)p; p += al256((size_t)NG * 64 * 4);
@@ -673,8 +743,9 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         G.ctl = (unsigned long long*)p; p += al256((8 + 4 * kSpread * kSpreadStride) * 8);
         G.drow = (int32_t* const*)p; p += al256(64 * 8);
         G.prow = (int32_t* const*)p; p += al256(64 * 8);
-        p += al256(64 * 4);
-        G.k = (uint32_t)gq.size();
+        G.start = (uint32_t*)p; p += al256(64 * 4);
+        G.k = (uint32_t)std::max<size_t>(gq.size(), joinable ? kcap : 0u);
+        G.kused = (uint32_t)gq.size();
         G.PS = (uint32_t*)p; p += al256((size_t)n * G.k * 4);
         G.DS = (uint32_t*)p; p += al256((size_t)n * G.k * 4);
         for (size_t j = 0; j < gq.size(); ++j) {
@@ -707,7 +778,11 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     for (int i = 0; i < NG; ++i) work += std::max<int64_t>(hg[i].n / 64, 1);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((work + kRWaves - 1) / kRWaves, o.grid));
     uint32_t r = 0;
-    int K = 8;  // rounds here take milliseconds: a completion check per batch is cheap
+    // rounds here take milliseconds: a completion check per batch is cheap;
+    // a group that admits arrivals checks every 4 rounds
+    int K = joinable ? 4 : 8;
+    int64_t round_limit = maxn + 2;
+    uint32_t kused = hg[0].kused;
     unsigned long long* hp = (unsigned long long*)pin;
     for (;;) {
         for (int i = 0; i < K; ++i)
@@ -726,9 +801,40 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
             for (int c = 0; c < kSpread; ++c) t += hp[(size_t)i * kSpread * kSpreadStride + c * kSpreadStride];
             active = (t >> 32) != 0;
         }
+        if (joinable && kused < hg[0].k) {
+            // round boundary r: queries waiting for this graph join the group
+            std::vector<MsQuery> add;
+            (*hook)(r, (int)(hg[0].k - kused), !active, &add);
+            if (!add.empty()) {
+                const uint32_t nadd = (uint32_t)std::min<size_t>(add.size(), hg[0].k - kused);
+                for (uint32_t i = 0; i < nadd; ++i) {
+                    hsrc[kused + i] = (uint32_t)add[i].src;
+                    rowsD[kused + i] = add[i].dist;
+                    rowsP[kused + i] = add[i].parent;
+                }
+                GB_HIP(hipMemcpyAsync((void*)(hg[0].drow + kused), &rowsD[kused], nadd * 8,
+                                      hipMemcpyHostToDevice, stream));
+                GB_HIP(hipMemcpyAsync((void*)(hg[0].prow + kused), &rowsP[kused], nadd * 8,
+                                      hipMemcpyHostToDevice, stream));
+                GB_HIP(hipMemcpyAsync(dsrcs + kused, &hsrc[kused], nadd * 4,
+                                      hipMemcpyHostToDevice, stream));
+                if (!active) {
+                    const int cg = (int)std::min<int64_t>(
+                        std::max<int64_t>((hg[0].n + kBlock - 1) / kBlock, 1), 4096);
+                    hipLaunchKernelGGL(ms_clear_frontiers_kernel, dim3(cg), dim3(kBlock), 0, stream,
+                                       dgroups, 0);
+                }
+                hipLaunchKernelGGL(ms_join_kernel, dim3(1), dim3(64), 0, stream, dgroups, 0, r,
+                                   dsrcs + kused, kused, nadd);
+                GB_HIP(hipGetLastError());
+                kused += nadd;
+                round_limit = (int64_t)r + maxn + 2;
+                active = true;
+            }
+        }
         if (!active) break;
-        if ((int64_t)r > maxn + 2) return set_error(GBGPU_E_HIP, "batched BFS did not terminate");
-        K = std::min(K * 2, 512);
+        if ((int64_t)r > round_limit) return set_error(GBGPU_E_HIP, "batched BFS did not terminate");
+        if (!joinable) K = std::min(K * 2, 512);
     }
     for (int i = 0; i < NG; ++i) {
         const int tg = (int)std::min<int64_t>(std::max<int64_t>((hg[i].n + 63) / 64, 1), 8192);
@@ -776,14 +882,16 @@ int run_ms(const std::vector<MsQuery>& qs, const gbgpu_opts& o, gbgpu_stats* st,
 }
 
 // One group (<= 64 queries on one graph) with caller-provided memory
-// (ms_query_bytes(n) device bytes, ms_pin_bytes() pinned bytes).
+// (ms_query_bytes(n, max(k, kcap)) device bytes, ms_pin_bytes() pinned
+// bytes); with a hook, up to kcap - k more queries may join it at round
+// boundaries.
 int run_ms_group_mem(const std::vector<MsQuery>& qs, void* mem, void* pin, const gbgpu_opts& o,
-                     hipStream_t stream, int* rounds) {
+                     hipStream_t stream, int* rounds, uint32_t kcap, const MsJoinHook* hook) {
     std::vector<std::vector<int>> groups(1);
     for (int i = 0; i < (int)qs.size(); ++i) groups[0].push_back(i);
     int launches = 0;
     *rounds = 0;
-    return ms_run_chunk(qs, groups, 0, 1, mem, pin, o, stream, rounds, &launches);
+    return ms_run_chunk(qs, groups, 0, 1, mem, pin, o, stream, rounds, &launches, kcap, hook);
 }
 
 // Queries answered one source at a time on each graph's own workspace
@@ -829,6 +937,50 @@ int gbgpu_bfs_multi(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist
     if (g->depth.load(std::memory_order_relaxed) > kDeepGraph)
         return run_singles(qs, opt, st, (hipStream_t)stream, false);
     return run_ms(qs, opt, st, (hipStream_t)stream, &g->multi);
+}
+
+// Diagnostic: a packed group of srcs[0 .. k0) joined by srcs[k0 .. k0+k1)
+// at the first round boundary at or after join_round (or when the group runs
+// out of work first); rows of dist / parent with stride n.
+int gbgpu_debug_bfs_join(gbgpu_graph g, const int32_t* srcs, int32_t k0, int32_t k1,
+                         int32_t join_round, int32_t* dist, int32_t* parent, void* stream) {
+    if (!g || !srcs || !dist || !parent) return set_error(GBGPU_E_INVALID, "bad argument");
+    if (k0 < 1 || k1 < 0 || k0 + k1 > 64 || join_round < 0)
+        return set_error(GBGPU_E_INVALID, "need k0 >= 1, k1 >= 0, k0 + k1 <= 64");
+    for (int i = 0; i < k0 + k1; ++i)
+        if (srcs[i] < 0 || srcs[i] >= g->n)
+            return set_error(GBGPU_E_INVALID, "source %d = %d out of range", i, srcs[i]);
+    gbgpu_opts opt = resolve_opts(nullptr);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g->mu);
+    GB_TRY(ensure_pull_plan(g));
+    const size_t bytes = ms_query_bytes(g->n, 64);
+    void* mem = nullptr;
+    void* pin = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess)
+        return set_error(GBGPU_E_NOMEM, "join test workspace of %zu bytes", bytes);
+    if (hipHostMalloc(&pin, ms_pin_bytes(), hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(mem);
+        return set_error(GBGPU_E_NOMEM, "pinned buffer allocation failed");
+    }
+    std::vector<MsQuery> qs, later;
+    for (int i = 0; i < k0 + k1; ++i)
+        (i < k0 ? qs : later)
+            .push_back(MsQuery{g, srcs[i], dist + (size_t)i * g->n, parent + (size_t)i * g->n});
+    bool joined = later.empty();
+    MsJoinHook hook = [&](uint32_t r, int room, bool idle, std::vector<MsQuery>* add) {
+        if (joined || ((int32_t)r < join_round && !idle) || room < (int)later.size()) return;
+        *add = later;
+        joined = true;
+    };
+    int rounds = 0;
+    const int st = run_ms_group_mem(qs, mem, pin, opt, s, &rounds, 64u, &hook);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    (void)hipHostFree(pin);
+    if (st != GBGPU_OK) return st;
+    if (!joined) return set_error(GBGPU_E_HIP, "the joining sources were never admitted");
+    return GBGPU_OK;
 }
 
 static std::mutex g_batch_mu;

@@ -43,7 +43,7 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
 size_t ms_query_bytes(int64_t n, int64_t k);
 size_t ms_pin_bytes();
 int run_ms_group_mem(const std::vector<MsQuery>& qs, void* mem, void* pin, const gbgpu_opts& o,
-                     hipStream_t stream, int* rounds);
+                     hipStream_t stream, int* rounds, uint32_t kcap, const MsJoinHook* hook);
 
 // Bucket capacity of a weighted query: the re-queue override, else the
 // option, else the default.
@@ -98,12 +98,13 @@ static void finish_query(gbgpu_server sv, const PendingQ& p, int status, int rou
     gbgpu_result r;
     memset(&r, 0, sizeof(r));
     r.status = status;
-    r.rounds = rounds;
+    r.rounds = rounds - p.join_round;
     r.t_arrive_ns = p.t_arrive;
-    r.t_start_ns = t_start;
+    r.t_start_ns = p.t_start ? p.t_start : t_start;
     r.t_done_ns = now_ns();
     r.retries = p.retries;
     r.batch = batch;
+    r.join_round = p.join_round;
     sv->done[p.ticket] = r;
     sv->live.erase(p.ticket);
 }
@@ -116,8 +117,10 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
         // pending BFS queries on its graph when they can be bit-packed)
         std::vector<PendingQ> job;
         size_t off = 0, bytes = 0;
+        uint32_t kcap = 0;
         while (!sv->stop) {
-            if (sched_admit(sv->pending, sv->alloc, sv->env, sv->wcap, &job, &off, &bytes)) break;
+            if (sched_admit(sv->pending, sv->alloc, sv->env, sv->wcap, &job, &off, &bytes, &kcap))
+                break;
             sv->cv.wait(lk);
         }
         if (job.empty()) break;  // stopping
@@ -132,7 +135,24 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
         if (job.size() > 1) {
             std::vector<MsQuery> qs;
             for (auto& p : job) qs.push_back(MsQuery{g, p.q.src, (int32_t*)p.q.dist, p.q.parent});
-            status = run_ms_group_mem(qs, mem, w->pin, sv->opts, w->stream, &rounds);
+            // BFS queries on this graph that arrive while the group runs join
+            // it at a round boundary, while it has free source slots
+            const int32_t gid = job[0].q.graph_id;
+            MsJoinHook hook = [&](uint32_t r, int room, bool, std::vector<MsQuery>* add) {
+                std::lock_guard<std::mutex> lk2(sv->mu);
+                if (sv->stop) return;
+                std::vector<PendingQ> got;
+                sched_take_bfs(sv->pending, gid, room, &got);
+                const int64_t t = now_ns();
+                for (auto& p : got) {
+                    p.t_start = t;
+                    p.join_round = (int32_t)r;
+                    add->push_back(MsQuery{g, p.q.src, (int32_t*)p.q.dist, p.q.parent});
+                    job.push_back(p);
+                }
+            };
+            status = run_ms_group_mem(qs, mem, w->pin, sv->opts, w->stream, &rounds, kcap,
+                                      kcap > job.size() ? &hook : nullptr);
         } else if (job[0].q.kind == GBGPU_QUERY_BFS) {
             bfs_ws_attach(w->bws, mem, g->n, g->nwords);
             gbgpu_stats st;
@@ -324,6 +344,8 @@ int gbgpu_submit(gbgpu_server sv, const gbgpu_query* q, uint64_t* ticket) {
     p.t_arrive = t;
     p.cap = 0;
     p.retries = 0;
+    p.t_start = 0;
+    p.join_round = 0;
     sv->pending.push_back(p);
     sv->live.insert(p.ticket);
     *ticket = p.ticket;

@@ -49,9 +49,10 @@ static void test_oldest_first_alone() {
     std::vector<uint32_t> cap = {0, 0};
     std::vector<PendingQ> job;
     size_t off = 0, bytes = 0;
-    CHECK(sched_admit(pend, a, fake_env({true, false}), cap, &job, &off, &bytes));
+    uint32_t kc = 0;
+    CHECK(sched_admit(pend, a, fake_env({true, false}), cap, &job, &off, &bytes, &kc));
     CHECK(job.size() == 1 && job[0].q.src == 5);  // graph 1 is not packable
-    CHECK(bytes == 256 * 100 && off == 0);
+    CHECK(bytes == 256 * 100 && off == 0 && kc == 0);
     CHECK(pend.size() == 1 && pend.front().q.src == 6);
 }
 
@@ -65,10 +66,12 @@ static void test_packs_same_graph_bfs_in_order() {
     std::vector<uint32_t> cap = {0, 0};
     std::vector<PendingQ> job;
     size_t off = 0, bytes = 0;
-    CHECK(sched_admit(pend, a, fake_env({true, false}), cap, &job, &off, &bytes));
+    uint32_t kc = 0;
+    CHECK(sched_admit(pend, a, fake_env({true, false}), cap, &job, &off, &bytes, &kc));
     CHECK(job.size() == 8);
     for (size_t i = 0; i < job.size(); ++i) CHECK(job[i].q.src == (int32_t)i);
-    CHECK(bytes == 256 * (20 + 480));
+    // the workspace fits a group of 64: later arrivals may join it
+    CHECK(bytes == 256 * (20 + 60 * 64) && kc == 64);
     // the others keep their order
     CHECK(pend.size() == 2 && pend[0].q.src == 100 && pend[1].q.src == 101);
 }
@@ -79,27 +82,44 @@ static void test_pack_limit_and_halving() {
     std::vector<uint32_t> cap = {0};
     std::vector<PendingQ> job;
     size_t off = 0, bytes = 0;
+    uint32_t kc = 0;
     {
         ArenaAlloc a(256 * 10000);
         std::deque<PendingQ> p = pend;
-        CHECK(sched_admit(p, a, fake_env({true}), cap, &job, &off, &bytes));
-        CHECK(job.size() == 64 && p.size() == 6 && p.front().q.src == 64);
+        CHECK(sched_admit(p, a, fake_env({true}), cap, &job, &off, &bytes, &kc));
+        CHECK(job.size() == 64 && p.size() == 6 && p.front().q.src == 64 && kc == 64);
     }
     {
         // room for 600 units: groups of 64, 32 and 16 do not fit, 8 does
+        // (and no room for arrivals to join)
         ArenaAlloc a(256 * 600);
         std::deque<PendingQ> p = pend;
-        CHECK(sched_admit(p, a, fake_env({true}), cap, &job, &off, &bytes));
-        CHECK(job.size() == 8 && bytes == 256 * 500);
+        CHECK(sched_admit(p, a, fake_env({true}), cap, &job, &off, &bytes, &kc));
+        CHECK(job.size() == 8 && bytes == 256 * 500 && kc == 8);
         CHECK(job.front().q.src == 0 && job.back().q.src == 7);
     }
     {
         // not even two fit (140 units): the oldest runs alone (100 units)
         ArenaAlloc a(256 * 120);
         std::deque<PendingQ> p = pend;
-        CHECK(sched_admit(p, a, fake_env({true}), cap, &job, &off, &bytes));
-        CHECK(job.size() == 1 && job[0].q.src == 0);
+        CHECK(sched_admit(p, a, fake_env({true}), cap, &job, &off, &bytes, &kc));
+        CHECK(job.size() == 1 && job[0].q.src == 0 && kc == 0);
     }
+}
+
+static void test_take_bfs_for_a_joining_round() {
+    // what a running group on graph 0 takes at a round boundary: the first
+    // BFS queries on graph 0, in order, up to its free slots; others stay
+    std::deque<PendingQ> pend = {q(0, GBGPU_QUERY_WBFS, 1), q(0, GBGPU_QUERY_BFS, 2),
+                                 q(1, GBGPU_QUERY_BFS, 3), q(0, GBGPU_QUERY_BFS, 4),
+                                 q(0, GBGPU_QUERY_BFS, 5)};
+    std::vector<PendingQ> got;
+    sched_take_bfs(pend, 0, 2, &got);
+    CHECK(got.size() == 2 && got[0].q.src == 2 && got[1].q.src == 4);
+    CHECK(pend.size() == 3 && pend[0].q.src == 1 && pend[1].q.src == 3 && pend[2].q.src == 5);
+    got.clear();
+    sched_take_bfs(pend, 0, 0, &got);
+    CHECK(got.empty() && pend.size() == 3);
 }
 
 static void test_head_of_line_waits_for_memory() {
@@ -110,12 +130,13 @@ static void test_head_of_line_waits_for_memory() {
     std::vector<uint32_t> cap = {0, 0};
     std::vector<PendingQ> job;
     size_t off = 0, bytes = 0;
-    CHECK(!sched_admit(pend, a, fake_env({false, false}), cap, &job, &off, &bytes));
+    uint32_t kc = 0;
+    CHECK(!sched_admit(pend, a, fake_env({false, false}), cap, &job, &off, &bytes, &kc));
     CHECK(job.empty() && pend.size() == 2 && pend.front().q.src == 1);
     CHECK(a.largest() == 256 * 200);
     // once memory is released (a larger arena here) it runs
     ArenaAlloc b(256 * 1000);
-    CHECK(sched_admit(pend, b, fake_env({false, false}), cap, &job, &off, &bytes));
+    CHECK(sched_admit(pend, b, fake_env({false, false}), cap, &job, &off, &bytes, &kc));
     CHECK(job.size() == 1 && job[0].q.src == 1 && bytes == 256 * 364);
 }
 
@@ -128,7 +149,8 @@ static void test_memory_accounting_over_a_run() {
     std::vector<PendingQ> job;
     std::vector<std::pair<size_t, size_t>> live;
     size_t off = 0, bytes = 0;
-    while (sched_admit(pend, a, fake_env({false, false}), cap, &job, &off, &bytes))
+    uint32_t kc = 0;
+    while (sched_admit(pend, a, fake_env({false, false}), cap, &job, &off, &bytes, &kc))
         live.emplace_back(off, bytes);
     CHECK(live.size() == 3 && pend.size() == 7);
     for (size_t i = 0; i < live.size(); ++i)
@@ -136,7 +158,7 @@ static void test_memory_accounting_over_a_run() {
             CHECK(live[i].first + live[i].second <= live[j].first ||
                   live[j].first + live[j].second <= live[i].first);
     a.release(live[1].first, live[1].second);
-    CHECK(sched_admit(pend, a, fake_env({false, false}), cap, &job, &off, &bytes));
+    CHECK(sched_admit(pend, a, fake_env({false, false}), cap, &job, &off, &bytes, &kc));
     CHECK(off == live[1].first);
 }
 
@@ -147,7 +169,8 @@ static void test_learned_capacity_and_requeue() {
     ArenaAlloc a(256 * 100000);
     std::vector<PendingQ> job;
     size_t off = 0, bytes = 0;
-    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes));
+    uint32_t kc = 0;
+    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes, &kc));
     CHECK(job.size() == 1 && job[0].cap == 0 && bytes == 256 * 364);
     // it overflowed capacity 64: back at the front with 128, one retry
     CHECK(sched_requeue_overflow(pend, env, cap, 256 * 100000, job[0], 64, 1000));
@@ -157,13 +180,13 @@ static void test_learned_capacity_and_requeue() {
     // a later weighted query on the same graph starts from the learned 128
     pend.push_back(q(1, GBGPU_QUERY_WBFS, 9));
     a.release(off, bytes);
-    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes));  // the re-queued one
+    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes, &kc));  // the re-queued one
     CHECK(job[0].q.src == 7 && job[0].cap == 128);
     a.release(off, bytes);
-    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes));  // the BFS
+    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes, &kc));  // the BFS
     CHECK(job[0].q.src == 8 && job[0].cap == 0);
     a.release(off, bytes);
-    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes));
+    CHECK(sched_admit(pend, a, env, cap, &job, &off, &bytes, &kc));
     CHECK(job[0].q.src == 9 && job[0].cap == 128 && job[0].retries == 0);
     // capacity doubles at most to n
     PendingQ big = job[0];
@@ -219,6 +242,7 @@ int main() {
     test_oldest_first_alone();
     test_packs_same_graph_bfs_in_order();
     test_pack_limit_and_halving();
+    test_take_bfs_for_a_joining_round();
     test_head_of_line_waits_for_memory();
     test_memory_accounting_over_a_run();
     test_learned_capacity_and_requeue();

@@ -128,3 +128,25 @@ def test_deep_graphs_batch_one_source_at_a_time(gb):
         od, op = oracle.bfs(h, s)
         assert np.array_equal(dists[q].cpu().numpy(), od), q
         assert np.array_equal(parents[q].cpu().numpy(), op), q
+
+
+@pytest.mark.parametrize("join_round", [0, 5, 9, 40])
+def test_sources_joining_a_running_group(gb, rmat14, join_round):
+    """Round-boundary admission: srcs[:5] start a packed group, the rest join
+    it at a later round (before the group has finished, or after it ran out
+    of work: join_round 40), with a repeated source among the joiners and a
+    joiner equal to a starting source.  Every row equals the oracle."""
+    g, G = rmat14
+    srcs = [int(x) for x in gg.sources(g, 12, seed=7)]
+    srcs = srcs[:5] + srcs[5:11] + [srcs[6], srcs[0]]
+    D, P = gb.bfs_join(G, srcs, 5, join_round)
+    check_rows(g, srcs, D, P, tag=f"join at {join_round}")
+
+
+def test_joining_on_deep_and_small_graphs(gb):
+    for g, k0, jr in ((gg.cycle(100), 2, 20), (gg.torus3d(8), 30, 4), (gg.path(7), 1, 0)):
+        G = gb.Graph.from_csr(g, with_weights=False)
+        srcs = (np.arange(min(g.n, 64), dtype=np.int32) * 7 + 3) % g.n
+        D, P = gb.bfs_join(G, srcs, k0, jr)
+        check_rows(g, srcs, D, P, tag=f"{g.name} join at {jr}")
+        G.free()

@@ -174,3 +174,55 @@ def test_server_errors(gb, graphs):
     assert again > 0
     wait(sv, tickets)
     sv.close()
+
+
+def test_arrivals_join_a_running_packed_group(gb):
+    """BFS arrivals on a graph whose packed group is running join it at a
+    round boundary (join_round > 0, one group start time for the starters).
+    A slow weighted query first holds the only worker, so two BFS queries on
+    a shallow 120-cycle (depth 61, known from a first search) start together
+    as a group with room for 64; ten more arrive while it runs.  Every result
+    equals the oracle whatever the timing; at least one of five attempts
+    must show a join."""
+    ring = gg.cycle(120)
+    R = gb.Graph.from_csr(ring, with_weights=False)
+    gb.bfs(R, 0)  # the graph's depth becomes known: packable
+    big = gg.rmat(16, seed=3).with_weights(16, seed=2)
+    B = gb.Graph.from_csr(big)
+    sv = gb.Server(arena_bytes=1 << 30, max_inflight=1)
+    rid, bid = sv.add_graph(R), sv.add_graph(B)
+    joined_any = False
+    for attempt in range(5):
+        outs = []
+
+        def submit(gid, kind, src, n):
+            d = torch.empty(n, dtype=torch.int32, device="cuda")
+            p = torch.empty(n, dtype=torch.int32, device="cuda")
+            outs.append((sv.submit(gid, kind, src, d, p), gid, kind, src, d, p))
+            return outs[-1][0]
+
+        blocker = submit(bid, gb.QUERY_WBFS, int(gg.sources(big, 1, seed=attempt + 1)[0]), big.n)
+        for s in (3 + attempt, 60):
+            submit(rid, gb.QUERY_BFS, s, ring.n)
+        while sv.poll(blocker) is None:
+            time.sleep(0.0001)
+        for s in range(10):
+            submit(rid, gb.QUERY_BFS, (11 * s + attempt) % ring.n, ring.n)
+        res = wait(sv, [o[0] for o in outs[1:]])
+        for t, gid, kind, s, d, p in outs[1:]:
+            assert res[t]["status"] == gb.OK
+            od, op = oracle.bfs(ring, s)
+            assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op), s
+        joins = [res[o[0]]["join_round"] for o in outs[1:]]
+        if any(j > 0 for j in joins):
+            joined_any = True
+            # the queries that joined report the group's size and later start
+            starters = [res[o[0]] for o in outs[1:3]]
+            late = [res[o[0]] for o in outs[3:] if res[o[0]]["join_round"] > 0]
+            assert all(r["batch"] >= 3 for r in starters + late)
+            assert all(r["t_start_ns"] > starters[0]["t_start_ns"] for r in late)
+            break
+    sv.close()
+    R.free()
+    B.free()
+    assert joined_any, "no arrival joined a running group in five attempts"
