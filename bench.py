@@ -603,11 +603,15 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
     try:
         w = gg.weights(g, 24, seed=2)
         Gw = gb.Graph(G.offsets, G.nbrs, w, validate=False)
+        # the weighted search takes its own tuned options (none: the
+        # library's defaults), not the BFS ones
+        wopts = tuned_opts(gb, Gw, g, srcs[0], "wbfs")
+        extra["wbfs_rmat24_opts"] = wopts
         tot_e, tot_t = 0, 0.0
         for s in srcs[:4]:
             d, p = gb.wbfs(Gw, s)
             e = int(deg[gb.as_u32(d) != 0xFFFFFFFF].sum()) // 2
-            t = timed(lambda: gb.wbfs(Gw, s, opts=user_opts), reps=2)
+            t = timed(lambda: gb.wbfs(Gw, s, opts=wopts), reps=2)
             tot_e += e
             tot_t += t
         extra["wbfs_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
@@ -691,7 +695,7 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         T = gb.Graph.from_csr(tg, validate=False)
         ts = int(gg.sources(tg, 1, seed=3)[0])
         topt_b = tuned_opts(gb, T, tg, ts, "bfs") or user_opts
-        topt_w = tuned_opts(gb, T, tg, ts, "wbfs") or user_opts
+        topt_w = tuned_opts(gb, T, tg, ts, "wbfs")
         tt = timed(lambda: gb.bfs(T, ts, opts=topt_b), reps=2)
         tw = timed(lambda: gb.wbfs(T, ts, opts=topt_w), reps=1)
         extra["torus256_opts"] = {"bfs": topt_b, "wbfs": topt_w}
