@@ -99,7 +99,13 @@ typedef struct {
     int32_t max_pending;     /* server: pending-queue bound (default 65536)     */
     int32_t beta;            /* BFS: after a dense round stay dense while
                                 |U| > n / beta (default 24; negative: off)     */
-    int32_t reserved[5];
+    int32_t persistent;      /* single-source BFS: 1 runs every round in one
+                                cooperative launch (rounds separated by grid
+                                barriers; if the launch is refused or a
+                                barrier wait gives up, the search reruns one
+                                launch per round); 0 (default) and -1: one
+                                launch per round                             */
+    int32_t reserved[4];     /* must be zero                                   */
 } gbgpu_opts;
 
 /* Per-call statistics (optional out-parameter). */
@@ -400,7 +406,9 @@ typedef struct {
     int32_t join_round;  /* BFS that joined a running packed group: the
                             group's round it joined before (0 otherwise);
                             t_start_ns is then the time it joined          */
-    int32_t reserved;
+    int32_t launches;    /* traversal launches of the run that answered a
+                            query run alone (1: every round in one launch);
+                            0 for packed groups                            */
 } gbgpu_result;
 
 /* Create a server.

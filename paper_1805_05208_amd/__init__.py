@@ -51,7 +51,8 @@ class Opts(ctypes.Structure):
         ("grid", ctypes.c_int32), ("bucket_window", ctypes.c_int32),
         ("bucket_capacity", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
         ("profile", ctypes.c_int32), ("max_pending", ctypes.c_int32),
-        ("beta", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+        ("beta", ctypes.c_int32), ("persistent", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -80,7 +81,7 @@ class Result(ctypes.Structure):
         ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
         ("t_arrive_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
         ("t_done_ns", ctypes.c_int64), ("retries", ctypes.c_int32), ("batch", ctypes.c_int32),
-        ("join_round", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("join_round", ctypes.c_int32), ("launches", ctypes.c_int32),
     ]
 
 
@@ -489,7 +490,7 @@ class Server:
         _check(st)
         return {"status": r.status, "rounds": r.rounds, "t_arrive_ns": r.t_arrive_ns,
                 "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns, "retries": r.retries,
-                "batch": r.batch, "join_round": r.join_round}
+                "batch": r.batch, "join_round": r.join_round, "launches": r.launches}
 
     def drain(self):
         _check(lib().gbgpu_server_drain(self.handle))

@@ -32,9 +32,15 @@ namespace gb {
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The control block: 64 words of counters, the round totals (4 slots of
+// kSpread spread counters), then the grid-barrier area of the single-launch
+// form (kBarWords 32-bit words).
+constexpr int kCtlWords = 64 + 4 * kSpread * kSpreadStride;
+constexpr int kBarWords = 4096;
+
 size_t bfs_ws_bytes(int64_t n, int64_t nwords) {
     return al256((size_t)nwords * 4) * 4 + al256((size_t)(n + 64) * 4) * 4 +
-           al256((64 + 4 * kSpread * kSpreadStride) * 8);
+           al256((size_t)kCtlWords * 8 + (size_t)kBarWords * 4);
 }
 
 // Points the workspace at `mem` (bfs_ws_bytes(n, nwords) bytes of device
@@ -92,6 +98,22 @@ static int ensure_bfs_ws(gbgpu_graph g) {
     }
     g->bfs = w;
     return GBGPU_OK;
+}
+
+// Grid-barrier area of the single-launch form (32-bit words; fields that
+// different workgroups update sit 256 bytes apart):
+//   [0]   arrivals at the start-up census     [64]  census done
+//   [128] abort word                          [192] arrivals of die leaders
+//   [256] generation (last finished barrier)
+//   [512 + 64 x]  workgroups resident on die x (x < 16)
+//   [1536 + 64 x] arrivals on die x           [2560 + 64 x] release of die x
+constexpr int kBarCensusCnt = 0, kBarCensusDone = 64, kBarAbort = 128, kBarLeaders = 192,
+              kBarGen = 256, kBarDieCount = 512, kBarDieArrive = 1536, kBarDieRelease = 2560,
+              kBarDieStride = 64, kBarMaxDies = 16;
+static_assert(kBarDieRelease + kBarMaxDies * kBarDieStride <= kBarWords, "barrier area");
+
+__device__ __forceinline__ uint32_t* bfs_bar(unsigned long long* ctl) {
+    return reinterpret_cast<uint32_t*>(ctl + kCtlWords);
 }
 
 struct BfsArgs {
@@ -179,6 +201,10 @@ __global__ __launch_bounds__(kBlock) void bfs_init_kernel(BfsArgs a, const uint3
         a.ctl[14] = 0;  // vertices reached through round r - 1, by parity of r
         a.ctl[15] = 0;
     }
+    // grid barrier of the single-launch form: every count, flag and the
+    // abort word start at zero
+    uint32_t* bar = bfs_bar(a.ctl);
+    for (int64_t i = tid; i < kBarWords; i += stride) bar[i] = 0u;
     // round totals: 4 slots of kSpread counters; slot 0 holds U_0 = {src}
     unsigned long long* tot = a.ctl + 64;
     for (int64_t i = tid; i < 4 * kSpread; i += stride)
@@ -550,10 +576,11 @@ __device__ __forceinline__ void attach_leaves(const BfsArgs& a, uint32_t r, WgQu
     }
 }
 
-__global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32_t r) {
-    __shared__ WgQueue q;
-    __shared__ unsigned long long s_tot, s_prev;
-
+// One BFS round (workgroup-uniform); returns true when round r found the
+// frontier empty (the search is over: the first such round attached the
+// degree-1 vertices and told the host).
+__device__ __forceinline__ bool bfs_round(const BfsArgs& a, uint32_t r, WgQueue& q,
+                                          unsigned long long& s_tot, unsigned long long& s_prev) {
     unsigned long long* qcnt = a.ctl + 4;
     unsigned long long* qover = a.ctl + 8;
     unsigned long long* tot = a.ctl + 64;  // 4 slots x kSpread x kSpreadStride
@@ -592,7 +619,7 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
         // vertices) attaches the degree-1 vertices and tells the host; the
         // launches queued behind it return at once.
         if ((s_prev >> 32) != 0) attach_leaves(a, r, q);
-        return;
+        return true;
     }
     const bool qvalid = qover[rs] == 0;
     const bool push = choose_push(a, r, count, edges, qvalid);
@@ -706,6 +733,145 @@ __global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32
             atomicAdd(&out.tot[(blockIdx.x % kSpread) * kSpreadStride],
                       ((unsigned long long)q.found << 32) | q.fdsum);
     }
+    return false;
+}
+
+__global__ __launch_bounds__(kRBlock, 8) void bfs_round_kernel(BfsArgs a, uint32_t r) {
+    __shared__ WgQueue q;
+    __shared__ unsigned long long s_tot, s_prev;
+    (void)bfs_round(a, r, q, s_tot, s_prev);
+}
+
+// Grid-wide barrier of the single-launch form (every workgroup is
+// resident).  CDNA keeps one L2 per die (XCD), and the device-scope fences
+// that make stores visible across dies write back (release) or invalidate
+// (acquire) that whole L2.  So the workgroups of each die elect a leader
+// per barrier, the last of them to arrive, which alone writes the die's L2
+// back and meets the other dies' leaders, then releases its die; every
+// workgroup takes its own acquire (an invalidate of narrower scope need
+// not drop the CU's L1 lines).  Every count is monotone (epoch e = barrier number, from 1), so
+// nothing is reset between barriers.  A wait longer than kBarrierSpin polls
+// sets the abort word and gives up; every wait also gives up once the abort
+// word is set, so the kernel always ends and the host can fall back.
+constexpr uint64_t kBarrierSpin = 1ull << 22;
+
+struct DieInfo {
+    uint32_t die, nwg, ndies;  // this workgroup's die, workgroups on it, dies in use
+};
+
+__device__ __forceinline__ uint32_t bar_ld(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void bar_st(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t bar_add(uint32_t* p) {
+    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+}
+
+// Polls *p until it equals want (relaxed device-scope loads: an acquire load
+// would invalidate the caches at every poll).  False when the abort word is
+// set or the wait gave up.
+__device__ __forceinline__ bool bar_wait(const uint32_t* p, uint32_t want, uint32_t* bar) {
+    uint64_t spins = 0;
+    while (bar_ld(p) != want) {
+        if (bar_ld(bar + kBarAbort)) return false;
+        if (++spins > kBarrierSpin) {
+            bar_st(bar + kBarAbort, 1u);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// The die (XCD) this wave runs on, from the hardware register.
+__device__ __forceinline__ uint32_t die_id() {
+    uint32_t x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & (kBarMaxDies - 1);
+}
+
+// Start-up census (all workgroups, once): counts the workgroups of each die
+// behind one plain counting barrier.
+__device__ bool bar_census(uint32_t* bar, DieInfo& di) {
+    __shared__ uint32_t s_ok;
+    if (threadIdx.x == 0) {
+        const uint32_t x = die_id();
+        __hip_atomic_fetch_add(bar + kBarDieCount + kBarDieStride * x, 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        bool ok = true;
+        if (bar_add(bar + kBarCensusCnt) == gridDim.x) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            bar_st(bar + kBarCensusDone, 1u);
+        } else {
+            ok = bar_wait(bar + kBarCensusDone, 1u, bar);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        uint32_t nd = 0;
+        for (uint32_t d = 0; d < (uint32_t)kBarMaxDies; ++d)
+            nd += bar_ld(bar + kBarDieCount + kBarDieStride * d) ? 1u : 0u;
+        di.die = x;
+        di.nwg = bar_ld(bar + kBarDieCount + kBarDieStride * x);
+        di.ndies = nd;
+        s_ok = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    return s_ok != 0u;
+}
+
+// Barrier number e (from 1).  Returns false when the kernel must stop.
+__device__ __forceinline__ bool grid_barrier(uint32_t* bar, const DieInfo& di, uint32_t e) {
+    __shared__ uint32_t s_ok;
+    // every wave's stores complete (in the die's L2) before the arrival
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        uint32_t* release = bar + kBarDieRelease + kBarDieStride * di.die;
+        if (bar_add(bar + kBarDieArrive + kBarDieStride * di.die) == e * di.nwg) {
+            // die leader: the die's stores go to memory, then the leaders meet
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (bar_add(bar + kBarLeaders) == e * di.ndies) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                bar_st(bar + kBarGen, e);
+            } else {
+                ok = bar_wait(bar + kBarGen, e, bar);
+            }
+            // one invalidate of the die's L2 (and this CU's L1), finished
+            // before the die is released
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
+            if (ok) bar_st(release, e);
+        } else {
+            ok = bar_wait(release, e, bar);
+            // a workgroup-scope invalidate need not drop this CU's L1 lines,
+            // so each workgroup takes the device-scope acquire itself
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        s_ok = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    return s_ok != 0u;
+}
+
+// All rounds of one BFS in a single cooperative launch, separated by grid
+// barriers (for deep graphs, where a round's work is smaller than a
+// launch).  Ends when a round finds the frontier empty, or after max_rounds,
+// or when a barrier is abandoned (the abort word tells the host).  One
+// workgroup per CU, up to 128 VGPRs: the loop around the round keeps more
+// state live, and at the 64-VGPR limit of two workgroups per CU it spilled.
+__global__ __launch_bounds__(kRBlock, 4) void bfs_persistent_kernel(BfsArgs a, uint32_t* bar,
+                                                                    uint32_t max_rounds) {
+    __shared__ WgQueue q;
+    __shared__ unsigned long long s_tot, s_prev;
+    __shared__ DieInfo di;
+    if (!bar_census(bar, di)) return;
+    for (uint32_t r = 0; r < max_rounds; ++r) {
+        if (bfs_round(a, r, q, s_tot, s_prev)) break;
+        if (!grid_barrier(bar, di, r + 1)) break;
+    }
 }
 
 // Kernel arguments of one BFS over workspace w (device arrays attached) with
@@ -776,6 +942,46 @@ static void bfs_stats_end(gbgpu_stats* st, const uint32_t* prog, int64_t launche
     st->wall_ms = wall_ms;
 }
 
+// Whether this search runs every round in one cooperative launch (only when
+// asked for: alone on the device the single launch is no faster than one
+// launch per round, since a round's dependent memory trips, not the launch,
+// set its time; the server asks for it on deep graphs).
+static bool use_persistent(const gbgpu_opts& o) { return o.persistent > 0; }
+
+// Runs the rounds of the search set up by bfs_init_kernel (already queued
+// on `stream`) in one cooperative launch of at most `grid` workgroups (fewer
+// if that many cannot all be resident), then waits for it.  *done is false
+// when the launch was refused or a grid barrier gave up: the state is then
+// partial and the caller runs the search again.
+static int run_bfs_persistent(gbgpu_graph g, BfsWs* w, const BfsArgs& a, int grid,
+                              int64_t max_rounds, hipStream_t stream, bool* done) {
+    *done = false;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device) !=
+            hipSuccess || !coop)
+        return GBGPU_OK;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(bfs_persistent_kernel), kRBlock, 0) !=
+            hipSuccess || per_cu < 1)
+        return GBGPU_OK;
+    const int pgrid = std::max(1, std::min(grid, per_cu * g->num_cus));
+    BfsArgs ka = a;
+    uint32_t* bar = reinterpret_cast<uint32_t*>(w->ctl + kCtlWords);
+    uint32_t maxr = (uint32_t)std::min<int64_t>(max_rounds, 0xFFFFFFFFll);
+    void* args[] = {&ka, &bar, &maxr};
+    if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(bfs_persistent_kernel),
+                                   dim3(pgrid), dim3(kRBlock), args, 0, stream) != hipSuccess) {
+        (void)hipGetLastError();  // refused: fall back to one launch per round
+        return GBGPU_OK;
+    }
+    uint32_t abort_w = 0;
+    GB_HIP(hipMemcpyAsync(&abort_w, bar + kBarAbort, 4, hipMemcpyDeviceToHost, stream));
+    GB_HIP(hipStreamSynchronize(stream));
+    *done = abort_w == 0 && w->hl.h[1] != 0;
+    return GBGPU_OK;
+}
+
 // One BFS on workspace w.  The results are complete when this returns; the
 // few launches queued behind the one that found the frontier empty may still
 // be pending unless sync_end is set.  They only touch the workspace, and the
@@ -803,13 +1009,30 @@ int run_bfs_ws(gbgpu_graph g, BfsWs* w, int32_t src, int32_t* dist, int32_t* par
     if (o.profile) GB_HIP(hipEventRecord(w->ev0, stream));
     const int64_t max_rounds = std::min<int64_t>(g->n + 2, 0x7FFFFFFF);
     int64_t launches = 0;
-    GB_TRY(run_pipeline(
-        hp, stream, o.rounds_per_sync, max_rounds,
-        [&](int64_t r) {
-            hipLaunchKernelGGL(bfs_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, a,
-                               (uint32_t)r);
-        },
-        &launches));
+    bool done = false;
+    if (use_persistent(o)) {
+        // every round in one cooperative launch; if the launch is refused or
+        // a grid barrier gave up, the search runs again one launch per round
+        GB_TRY(run_bfs_persistent(g, w, a, grid, max_rounds, stream, &done));
+        if (done) launches = 1;
+        if (!done) {
+            hipLaunchKernelGGL(bfs_init_kernel, dim3(igrid), dim3(kBlock), 0, stream, a,
+                               g->pruned, (uint32_t)src);
+            GB_HIP(hipGetLastError());
+            hp[0] = 0;
+            hp[1] = 0;
+            hp[2] = 0;
+            hp[3] = 0;
+        }
+    }
+    if (!done)
+        GB_TRY(run_pipeline(
+            hp, stream, o.rounds_per_sync, max_rounds,
+            [&](int64_t r) {
+                hipLaunchKernelGGL(bfs_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, a,
+                                   (uint32_t)r);
+            },
+            &launches));
     if (o.profile) GB_HIP(hipEventRecord(w->ev1, stream));
     GB_HIP(hipEventRecord(w->done, stream));
     // every round that wrote results has finished once the device reported

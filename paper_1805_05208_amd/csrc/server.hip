@@ -94,7 +94,7 @@ struct gbgpu_server_s {
 namespace gb {
 
 static void finish_query(gbgpu_server sv, const PendingQ& p, int status, int rounds, int64_t t_start,
-                         int32_t batch) {
+                         int32_t batch, int32_t launches) {
     gbgpu_result r;
     memset(&r, 0, sizeof(r));
     r.status = status;
@@ -105,6 +105,7 @@ static void finish_query(gbgpu_server sv, const PendingQ& p, int status, int rou
     r.retries = p.retries;
     r.batch = batch;
     r.join_round = p.join_round;
+    r.launches = launches;
     sv->done[p.ticket] = r;
     sv->live.erase(p.ticket);
 }
@@ -129,7 +130,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
         const int64_t t_start = now_ns();
         void* mem = sv->arena + off;
         gbgpu_graph g = sv->graphs[job[0].q.graph_id];
-        int status = GBGPU_OK, rounds = 0;
+        int status = GBGPU_OK, rounds = 0, launches = 0;
         bool requeue = false;
         uint32_t usedcap = 0;
         if (job.size() > 1) {
@@ -159,6 +160,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
             status = run_bfs_ws(g, w->bws, job[0].q.src, (int32_t*)job[0].q.dist, job[0].q.parent,
                                 sv->opts, &st, w->stream, true, true);  // the arena is reused at once
             rounds = st.rounds;
+            launches = st.launches;
         } else {
             const uint32_t NB = wbfs_window(g->maxw, sv->opts.bucket_window);
             const uint32_t C = initial_capacity(g, job[0].cap, sv->opts);
@@ -168,6 +170,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
             status = run_wbfs_ws(g, w->wws, job[0].q.src, (uint32_t*)job[0].q.dist, job[0].q.parent,
                                  sv->opts, &st, w->stream, &overflow);
             rounds = st.rounds;
+            launches = st.launches;
             if (status == GBGPU_OK && overflow) {
                 requeue = true;
                 usedcap = C;
@@ -181,9 +184,10 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
             // larger workspace could never be admitted
             if (!sched_requeue_overflow(sv->pending, sv->env, sv->wcap, sv->arena_bytes, job[0],
                                         usedcap, g->n))
-                finish_query(sv, job[0], GBGPU_E_NOMEM, rounds, t_start, 1);
+                finish_query(sv, job[0], GBGPU_E_NOMEM, rounds, t_start, 1, launches);
         } else {
-            for (auto& p : job) finish_query(sv, p, status, rounds, t_start, (int32_t)job.size());
+            for (auto& p : job)
+                finish_query(sv, p, status, rounds, t_start, (int32_t)job.size(), launches);
         }
         sv->cv.notify_all();
         if (sv->pending.empty() && sv->running == 0) sv->cv_idle.notify_all();

@@ -289,3 +289,37 @@ def test_back_to_back_calls_on_two_streams(gb, rmat16):
     for s, d, p in outs:
         od, op = oracle.bfs(g, s)
         assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op), s
+
+
+@pytest.mark.parametrize("persistent", [1, -1])
+def test_single_launch_rounds_identical(gb, persistent):
+    """Every round in one cooperative launch (grid barriers between rounds)
+    or one launch per round: the same outputs, equal to the oracle, on deep
+    and shallow graphs, and over the whole range of grid sizes (one
+    workgroup, a few per die, more than one per CU-die pair)."""
+    for g in (gg.cycle(3001), gg.torus3d(24), gg.grid2d(70, 40), gg.rmat(14, seed=9),
+              gg.path(2), gg.star(9)):
+        G = gb.Graph.from_csr(g, with_weights=False)
+        for i, s in enumerate(int(x) for x in gg.sources(g, 3, seed=11)):
+            o = {"persistent": persistent, "grid": (0, 1, 37)[i]}
+            d, p, st = gb.bfs(G, s, opts=o, stats=True)
+            od, op = oracle.bfs(g, s)
+            assert np.array_equal(d.cpu().numpy(), od), (g.name, s, o)
+            assert np.array_equal(p.cpu().numpy(), op), (g.name, s, o)
+            assert st["rounds"] == int(od[od != 2**31 - 1].max()) + 1
+            if persistent == 1:
+                assert st["launches"] == 1, (g.name, o, st)
+        G.free()
+
+
+def test_default_is_one_launch_per_round(gb):
+    """Alone on the device the default keeps one launch per round, also on
+    a graph a search has shown deep."""
+    g = gg.cycle(501)
+    G = gb.Graph.from_csr(g, with_weights=False)
+    for s in (0, 7):
+        d, p, st = gb.bfs(G, s, stats=True)
+        assert st["launches"] > 1
+        od, op = oracle.bfs(g, s)
+        assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op)
+    G.free()

@@ -226,3 +226,38 @@ def test_arrivals_join_a_running_packed_group(gb):
     R.free()
     B.free()
     assert joined_any, "no arrival joined a running group in five attempts"
+
+
+@pytest.mark.skip(reason="the server's single-launch BFS is not run: a serving benchmark "
+                         "process that used it (deep graphs, 128 workgroups) ended in a "
+                         "segmentation fault at exit after every result had been verified; "
+                         "the cause is not found, so the path stays off")
+def test_bfs_served_in_one_launch(gb):
+    """A server created with persistent = 1 runs its BFS queries as one
+    launch each (every round behind grid barriers), beside queries on
+    other graphs; with the default, one launch per round.  Every result
+    equals the oracle."""
+    deep, shallow = gg.grid2d(300, 20), gg.rmat(12, seed=8)
+    Gd = gb.Graph.from_csr(deep, with_weights=False)
+    Gs = gb.Graph.from_csr(shallow, with_weights=False)
+    for opts, single in (({"persistent": 1}, True), (None, False)):
+        sv = gb.Server(arena_bytes=64 << 20, max_inflight=4, opts=opts)
+        gd, gs_ = sv.add_graph(Gd), sv.add_graph(Gs)
+        ss = [int(x) for x in gg.sources(shallow, 4, seed=3)]
+        out = []
+        for gid, g, s in ((gd, deep, 150), (gs_, shallow, ss[0]), (gd, deep, 4321),
+                          (gs_, shallow, ss[1]), (gd, deep, 5999)):
+            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            out.append((sv.submit(gid, gb.QUERY_BFS, s, d, p), g, s, d, p))
+        res = wait(sv, [o[0] for o in out])
+        for t, g, s, d, p in out:
+            assert res[t]["status"] == gb.OK
+            od, op = oracle.bfs(g, s)
+            assert np.array_equal(d.cpu().numpy(), od), (g.name, s)
+            assert np.array_equal(p.cpu().numpy(), op), (g.name, s)
+            if g is deep:
+                assert (res[t]["launches"] == 1) == single, res[t]
+        sv.close()
+    Gd.free()
+    Gs.free()
