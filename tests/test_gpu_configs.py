@@ -34,7 +34,7 @@ torch = pytest.importorskip("torch")
 
 TUNED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                      "paper_1805_05208_amd", "tuned.json")
-# the GPU machines give one process 16 host cores
+# oracle threads: one process may use up to 16 host cores
 WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 
