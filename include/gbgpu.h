@@ -99,12 +99,13 @@ typedef struct {
     int32_t max_pending;     /* server: pending-queue bound (default 65536)     */
     int32_t beta;            /* BFS: after a dense round stay dense while
                                 |U| > n / beta (default 24; negative: off)     */
-    int32_t persistent;      /* single-source BFS: 1 runs every round in one
-                                cooperative launch (rounds separated by grid
-                                barriers; if the launch is refused or a
-                                barrier wait gives up, the search reruns one
-                                launch per round); 0 (default) and -1: one
-                                launch per round                             */
+    int32_t persistent;      /* BFS and batched BFS: 1 runs every round in
+                                one cooperative launch (rounds separated by
+                                grid barriers; batched groups drop out as
+                                their frontiers empty; if the launch is
+                                refused or a barrier wait gives up, the work
+                                reruns one launch per round); 0 (default) and
+                                -1: one launch per round                      */
     int32_t reserved[4];     /* must be zero                                   */
 } gbgpu_opts;
 
@@ -361,7 +362,11 @@ int gbgpu_bfs_multi(gbgpu_graph g, const int32_t* srcs, int32_t k,
  * per vertex and group), and one kernel launch per round advances every
  * group of every graph (up to 64 groups per launch), each group choosing
  * push or pull for itself; a group whose frontier is empty costs nothing.
- * The host checks for the end after 8, 16, 32, ... launches.  Queries on
+ * The host checks for the end after 8, 16, 32, ... launches.  With
+ * opts->persistent = 1 every round of those groups runs in one cooperative
+ * launch instead, a grid barrier between rounds, ending at the first round
+ * in which no group has a frontier (st->launches then counts one launch per
+ * 64 groups).  Queries on
  * graphs a single-source BFS has shown to be deeper than 64 levels run one
  * source at a time instead.
  *   graphs   host array of nq graph handles (repeats allowed, any sizes)

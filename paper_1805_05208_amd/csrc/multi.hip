@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "emit.h"
+#include "gridbar.h"
 
 namespace gb {
 
@@ -507,14 +508,27 @@ __device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, u
 // for a window of edges then stays in registers; at the 64-VGPR limit of
 // two workgroups per CU it spilled to scratch, and the spill traffic cost
 // more than the lost occupancy.
-__global__ __launch_bounds__(kRBlock, 1) void ms_round_kernel(MsArgs A, uint32_t r) {
-    __shared__ uint32_t s_units[kMaxGroups + 1];
-    __shared__ uint32_t s_push[kMaxGroups];
-    __shared__ uint32_t s_wc[kMaxGroups];
-    __shared__ unsigned long long s_tot[kMaxGroups];
-    __shared__ uint32_t s_emit[kMaxGroups];
-    __shared__ uint32_t s_found[kMaxGroups];
-    __shared__ uint32_t s_fdsum[kMaxGroups];
+// Workgroup state of one batched round.
+struct MsShared {
+    uint32_t units[kMaxGroups + 1];
+    uint32_t push[kMaxGroups];
+    uint32_t wc[kMaxGroups];
+    unsigned long long tot[kMaxGroups];
+    uint32_t emit[kMaxGroups];
+    uint32_t found[kMaxGroups];
+    uint32_t fdsum[kMaxGroups];
+};
+
+// One round r for every group (workgroup-uniform); returns false when no
+// group has a frontier in round r (every group has finished).
+__device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& sh) {
+    uint32_t* s_units = sh.units;
+    uint32_t* s_push = sh.push;
+    uint32_t* s_wc = sh.wc;
+    unsigned long long* s_tot = sh.tot;
+    uint32_t* s_emit = sh.emit;
+    uint32_t* s_found = sh.found;
+    uint32_t* s_fdsum = sh.fdsum;
     const int l = lane_id();
     const int wib = threadIdx.x / kWave;
     const uint32_t nwaves = gridDim.x * kRWaves;
@@ -648,6 +662,38 @@ __global__ __launch_bounds__(kRBlock, 1) void ms_round_kernel(MsArgs A, uint32_t
         atomicAdd(&ms_tot(G, r + 1)[(blockIdx.x % kSpread) * kSpreadStride],
                   ((unsigned long long)s_found[threadIdx.x] << 32) | s_fdsum[threadIdx.x]);
     }
+    bool any = false;
+    for (int g = 0; g < NG; ++g) any |= (s_tot[g] >> 32) != 0ull;
+    return any;
+}
+
+__global__ __launch_bounds__(kRBlock, 1) void ms_round_kernel(MsArgs A, uint32_t r) {
+    __shared__ MsShared sh;
+    (void)ms_round(A, r, sh);
+}
+
+// Every round of every group in one cooperative launch, a grid barrier
+// between rounds; groups drop out as their frontiers empty and the kernel
+// ends at the first round in which no group has a frontier (its number goes
+// to bar[kBarUser]), after max_rounds, or when a barrier wait gave up (the
+// abort word tells the host, which then runs the rounds one launch each).
+__global__ __launch_bounds__(kRBlock, 1) void ms_persistent_kernel(MsArgs A, uint32_t* bar,
+                                                                  uint32_t max_rounds) {
+    __shared__ MsShared sh;
+    __shared__ DieInfo di;
+    if (!bar_census(bar, di)) return;
+    uint32_t r = 0;
+    for (; r < max_rounds; ++r) {
+        if (!ms_round(A, r, sh)) break;
+        if (!grid_barrier(bar, di, r + 1)) return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) bar[kBarUser] = r;
+}
+
+// Zeroes a grid-barrier area (kBarWords words).
+__global__ void ms_bar_clear_kernel(uint32_t* bar) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kBarWords; i += gridDim.x * blockDim.x)
+        bar[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -685,7 +731,7 @@ static std::vector<std::vector<int>> ms_plan(const std::vector<MsQuery>& qs) {
 
 static size_t ms_header_bytes(int NG) {
     return al256(sizeof(MsGroupDev) * NG) + al256((size_t)NG * 64 * 4) +
-           al256(4096 * kMaxGroups * 4);
+           al256(4096 * kMaxGroups * 4) + al256((size_t)kBarWords * 4);
 }
 
 // Device bytes needed to run `groups` (at most kMaxGroups) together.
@@ -701,7 +747,50 @@ size_t ms_query_bytes(int64_t n, int64_t k) { return ms_header_bytes(1) + ms_gro
 
 size_t ms_pin_bytes() { return (size_t)kMaxGroups * kSpread * kSpreadStride * 8; }
 
-// Runs groups[g0 .. g0+NG) in one launch per round, with `mem` holding
+// Runs every round of the groups in A (initialised and seeded on `stream`)
+// in one cooperative launch of at most `grid` workgroups (fewer if that many
+// cannot all be resident), then waits for it.  *done is false when the
+// launch was refused or a barrier wait gave up: the groups' state is then
+// partial and the caller starts them again.  *rounds is the first round in
+// which no group had a frontier.  `hp` is pinned host memory (two words).
+static int ms_run_persistent(const MsArgs& A, uint32_t* dbar, int grid, gbgpu_graph g,
+                             int64_t max_rounds, unsigned long long* hp, hipStream_t stream,
+                             bool* done, uint32_t* rounds) {
+    *done = false;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device) !=
+            hipSuccess || !coop)
+        return GBGPU_OK;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(ms_persistent_kernel), kRBlock, 0) !=
+            hipSuccess || per_cu < 1)
+        return GBGPU_OK;
+    const int pgrid = std::max(1, std::min(grid, per_cu * g->num_cus));
+    hipLaunchKernelGGL(ms_bar_clear_kernel, dim3(4), dim3(kBlock), 0, stream, dbar);
+    GB_HIP(hipGetLastError());
+    MsArgs ka = A;
+    uint32_t* bar = dbar;
+    uint32_t maxr = (uint32_t)std::min<int64_t>(max_rounds, 0xFFFFFFFFll);
+    void* args[] = {&ka, &bar, &maxr};
+    if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(ms_persistent_kernel),
+                                   dim3(pgrid), dim3(kRBlock), args, 0, stream) != hipSuccess) {
+        (void)hipGetLastError();  // refused: the caller runs one launch per round
+        return GBGPU_OK;
+    }
+    uint32_t* h = reinterpret_cast<uint32_t*>(hp);
+    GB_HIP(hipMemcpyAsync(h, dbar + kBarAbort, 4, hipMemcpyDeviceToHost, stream));
+    GB_HIP(hipMemcpyAsync(h + 1, dbar + kBarUser, 4, hipMemcpyDeviceToHost, stream));
+    GB_HIP(hipStreamSynchronize(stream));
+    if (h[0] != 0u) return GBGPU_OK;
+    if ((int64_t)h[1] >= max_rounds) return set_error(GBGPU_E_HIP, "batched BFS did not terminate");
+    *rounds = h[1];
+    *done = true;
+    return GBGPU_OK;
+}
+
+// Runs groups[g0 .. g0+NG) in one launch per round (or, when opts.persistent
+// is 1 and no hook is given, every round in one launch), with `mem` holding
 // ms_chunk_bytes() bytes of device memory and `pin` ms_pin_bytes() of pinned
 // host memory.
 // With a join hook (one group only) the group's staging holds kcap sources
@@ -717,6 +806,7 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     MsGroupDev* dgroups = (MsGroupDev*)p; p += al256(sizeof(MsGroupDev) * NG);
     uint32_t* dsrcs = (uint32_t*)p; p += al256((size_t)NG * 64 * 4);
     uint32_t* dlog = (uint32_t*)p; p += al256(4096 * kMaxGroups * 4);
+    uint32_t* dbar = (uint32_t*)p; p += al256((size_t)kBarWords * 4);
     std::vector<MsGroupDev> hg(NG);
     std::vector<uint32_t> hsrc((size_t)NG * 64, 0);
     std::vector<int32_t*> rowsD((size_t)NG * 64, nullptr), rowsP((size_t)NG * 64, nullptr);
@@ -758,15 +848,19 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     }
     GB_HIP(hipMemcpyAsync(dgroups, hg.data(), sizeof(MsGroupDev) * NG, hipMemcpyHostToDevice, stream));
     GB_HIP(hipMemcpyAsync(dsrcs, hsrc.data(), (size_t)NG * 64 * 4, hipMemcpyHostToDevice, stream));
-    for (int i = 0; i < NG; ++i) {
-        const int k = (int)groups[gb0 + i].size();
-        const int ig = (int)std::min<int64_t>(std::max<int64_t>((hg[i].n + kBlock - 1) / kBlock, 1), 4096);
-        hipLaunchKernelGGL(ms_init_kernel, dim3(ig), dim3(kBlock), 0, stream, dgroups, i,
-                           dsrcs + (size_t)i * 64, k);
-        hipLaunchKernelGGL(ms_seed_kernel, dim3(1), dim3(64), 0, stream, dgroups, i,
-                           dsrcs + (size_t)i * 64, k);
-    }
-    GB_HIP(hipGetLastError());
+    auto init_groups = [&]() {
+        for (int i = 0; i < NG; ++i) {
+            const int k = (int)groups[gb0 + i].size();
+            const int ig =
+                (int)std::min<int64_t>(std::max<int64_t>((hg[i].n + kBlock - 1) / kBlock, 1), 4096);
+            hipLaunchKernelGGL(ms_init_kernel, dim3(ig), dim3(kBlock), 0, stream, dgroups, i,
+                               dsrcs + (size_t)i * 64, k);
+            hipLaunchKernelGGL(ms_seed_kernel, dim3(1), dim3(64), 0, stream, dgroups, i,
+                               dsrcs + (size_t)i * 64, k);
+        }
+        return hipGetLastError();
+    };
+    GB_HIP(init_groups());
     MsArgs A;
     A.groups = dgroups;
     A.ngroups = NG;
@@ -778,13 +872,26 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     for (int i = 0; i < NG; ++i) work += std::max<int64_t>(hg[i].n / 64, 1);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((work + kRWaves - 1) / kRWaves, o.grid));
     uint32_t r = 0;
+    int64_t round_limit = maxn + 2;
+    unsigned long long* hp = (unsigned long long*)pin;
+    bool done = false;
+    if (o.persistent > 0 && !joinable) {
+        // every round in one cooperative launch; if the launch is refused or
+        // a barrier wait gave up, the groups start again one launch per round
+        GB_TRY(ms_run_persistent(A, dbar, grid, qs[groups[gb0][0]].g, round_limit, hp, stream,
+                                 &done, &r));
+        if (done) {
+            *launches_out += 1;
+        } else {
+            r = 0;
+            GB_HIP(init_groups());
+        }
+    }
     // rounds here take milliseconds: a completion check per batch is cheap;
     // a group that admits arrivals checks every 4 rounds
     int K = joinable ? 4 : 8;
-    int64_t round_limit = maxn + 2;
     uint32_t kused = hg[0].kused;
-    unsigned long long* hp = (unsigned long long*)pin;
-    for (;;) {
+    while (!done) {
         for (int i = 0; i < K; ++i)
             hipLaunchKernelGGL(ms_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, A, r + i);
         GB_HIP(hipGetLastError());

@@ -150,3 +150,49 @@ def test_joining_on_deep_and_small_graphs(gb):
         D, P = gb.bfs_join(G, srcs, k0, jr)
         check_rows(g, srcs, D, P, tag=f"{g.name} join at {jr}")
         G.free()
+
+
+@pytest.mark.parametrize("k", [1, 7, 64, 130])
+def test_single_launch_batches_match_oracle(gb, rmat14, k):
+    """Every round of every group in one cooperative launch (grid barriers
+    between rounds, groups dropping out as their frontiers empty): the same
+    rows as the oracle, in one launch."""
+    g, G = rmat14
+    srcs = gg.sources(g, k, seed=3)
+    D, P, st = gb.bfs_multi(G, srcs, opts={"persistent": 1}, stats=True)
+    check_rows(g, srcs, D, P, tag=f"single launch k={k}")
+    assert st["launches"] == 1, st
+
+
+@pytest.mark.parametrize("force", [1, 2])
+def test_single_launch_batches_forced_directions(gb, rmat14, force):
+    g, G = rmat14
+    srcs = gg.sources(g, 40, seed=5)
+    D, P = gb.bfs_multi(G, srcs, opts={"persistent": 1, "force_direction": force, "grid": 37})
+    check_rows(g, srcs, D, P, tag=f"single launch force{force}")
+
+
+def test_single_launch_uneven_batch_and_small_graphs(gb):
+    """The uneven multi-graph batch in one launch (groups of different
+    graphs finishing at different rounds), and small graphs whose grid is a
+    single workgroup."""
+    scales = [8, 9, 10, 11, 12, 13, 14, 10]
+    graphs = [gg.rmat(s, seed=30 + i) for i, s in enumerate(scales)]
+    Gs = [gb.Graph.from_csr(g) for g in graphs]
+    qg, qs = [], []
+    for i, g in enumerate(graphs):
+        for s in gg.sources(g, 32 if i != 3 else 70, seed=40 + i):
+            qg.append(i)
+            qs.append(int(s))
+    dists, parents, st = gb.bfs_batch([Gs[i] for i in qg], qs, opts={"persistent": 1},
+                                      stats=True)
+    for q in range(len(qg)):
+        od, op = oracle.bfs(graphs[qg[q]], qs[q])
+        assert np.array_equal(dists[q].cpu().numpy(), od), q
+        assert np.array_equal(parents[q].cpu().numpy(), op), q
+    assert st["launches"] >= 1
+    for g in (gg.torus3d(10), gg.cycle(12), gg.path(3), gg.star(5)):
+        G = gb.Graph.from_csr(g)
+        srcs = np.arange(min(g.n, 70), dtype=np.int32) % g.n
+        D, P = gb.bfs_multi(G, srcs, opts={"persistent": 1})
+        check_rows(g, srcs, D, P, tag=f"single launch {g.name}")
