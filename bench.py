@@ -8,7 +8,8 @@ oracle timed on the host as the CPU baseline.  Extra sections (weighted BFS,
 the 3-D torus, batched queries, serving latency) are reported under "extra".
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--scale 24]
-       [--no-extra] [--no-cpu]
+       [--no-extra] [--no-cpu] [--only SECTION] [--serving-queries N]
+       python bench.py --pmc-summary DIR | --trace-summary DIR
 """
 from __future__ import annotations
 
@@ -199,6 +200,11 @@ def main():
                     help="run a 1 GiB device copy first (calibrates HBM byte counters)")
     ap.add_argument("--pmc-summary", type=str, default="",
                     help="print per-kernel averages of a rocprofv3 --pmc csv directory and exit")
+    ap.add_argument("--trace-summary", type=str, default="",
+                    help="print per-kernel totals and device concurrency of a rocprofv3 "
+                         "--kernel-trace csv directory and exit")
+    ap.add_argument("--serving-queries", type=int, default=2000,
+                    help="Poisson arrivals per offered load in the serving section")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
     ap.add_argument("--only", choices=["connectivity", "compressed", "wbfs", "sssp", "bc",
@@ -208,6 +214,9 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
         return
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -333,7 +342,8 @@ def main():
         return
     if args.only == "serving":
         res = {"metric": "serving_section", "config": {"workload": "six resident graphs"}}
-        res.update(run_serving(g, G, gg, gb, torch))
+        res.update(run_serving(g, G, gg, gb, torch, nq=args.serving_queries,
+                               cpu=not args.no_cpu))
         print(json.dumps(res), flush=True)
         return
     if args.only == "connectivity":
@@ -569,6 +579,71 @@ def pmc_summary(path):
                 acc[k][1].add(row["Dispatch_Id"])
     for (kern, ctr), (tot, ids) in sorted(acc.items(), key=lambda kv: -kv[1][0]):
         print(f"{ctr:12s} dispatches={len(ids):6d} mean={tot / len(ids):14.1f}  {kern}")
+
+
+def trace_summary(path, window_s=1.0):
+    """Kernel time by kernel, and how much kernels overlapped on the device,
+    from the kernel_trace csv files rocprofv3 wrote under `path`:
+    concurrency = sum of kernel durations / time at least one kernel ran,
+    overall and per window of `window_s` seconds."""
+    import csv
+    import glob
+    from collections import defaultdict
+    per = defaultdict(lambda: [0, 0])
+    iv = []
+    for f in glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                a, b = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+                k = row["Kernel_Name"].split("(")[0][:70]
+                per[k][0] += 1
+                per[k][1] += b - a
+                iv.append((a, b))
+    if not iv:
+        print("no kernel trace under", path)
+        return
+    iv.sort()
+    t0, t1 = iv[0][0], max(b for _, b in iv)
+    tot = sum(b - a for a, b in iv)
+    print(f"{len(iv)} kernels over {(t1 - t0) / 1e9:.3f} s, {tot / 1e9:.3f} s of kernel time")
+    for k, (n, ns) in sorted(per.items(), key=lambda kv: -kv[1][1])[:16]:
+        print(f"  {k:70s} calls={n:8d} total={ns / 1e6:10.2f} ms avg={ns / n / 1e3:9.2f} us "
+              f"{100.0 * ns / tot:5.1f} %")
+    # busy time (union of the intervals), overall and per window
+    w = int(window_s * 1e9)
+    nwin = (t1 - t0) // w + 1
+    busy = [0] * nwin
+    work = [0] * nwin
+    for a, b in iv:
+        x = a
+        while x < b:
+            i = (x - t0) // w
+            e = min(b, t0 + (i + 1) * w)
+            work[i] += e - x
+            x = e
+    cur_a, cur_b = iv[0]
+    merged = []
+    for a, b in iv[1:]:
+        if a > cur_b:
+            merged.append((cur_a, cur_b))
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    merged.append((cur_a, cur_b))
+    for a, b in merged:
+        x = a
+        while x < b:
+            i = (x - t0) // w
+            e = min(b, t0 + (i + 1) * w)
+            busy[i] += e - x
+            x = e
+    tb = sum(busy)
+    print(f"device busy {tb / 1e9:.3f} s ({100.0 * tb / (t1 - t0):.1f} % of the span), "
+          f"mean concurrency {tot / max(tb, 1):.2f}")
+    print("window  busy%  concurrency")
+    for i in range(nwin):
+        if busy[i]:
+            print(f"{i * window_s:6.0f}  {100.0 * busy[i] / w:5.1f}  {work[i] / busy[i]:6.2f}")
 
 
 TUNED = os.path.join(ROOT, "paper_1805_05208_amd", "tuned.json")
@@ -881,7 +956,7 @@ class ServedMix:
         return out
 
 
-def run_serving(g, G, gg, gb, torch, nq=2000):
+def run_serving(g, G, gg, gb, torch, nq=2000, cpu=True):
     """Poisson arrivals of mixed BFS / weighted BFS queries on the six
     resident graphs, at 0.5x and 0.8x of the saturated rate, every served
     result verified against the standalone call."""
@@ -971,6 +1046,8 @@ def run_serving(g, G, gg, gb, torch, nq=2000):
     res["serving_verified_digest"] = mix.verified_digest
     res["serving_verified_full"] = mix.verified_full
     sv.close()
+    if not cpu:
+        return res
 
     # the oracle on every host core: a seeded sample of the same mix, one
     # query per thread
