@@ -1,6 +1,6 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a
-message before anything touches a device, and the pmc summary mode reads a
-counter CSV without a GPU."""
+message before anything touches a device, and the pmc and trace summary
+modes read rocprofv3 CSVs without a GPU."""
 import os
 import subprocess
 import sys
@@ -28,3 +28,23 @@ def test_pmc_summary_reads_a_counter_csv(tmp_path):
     assert r.returncode == 0, r.stderr
     line = [l for l in r.stdout.splitlines() if "bfs_round_kernel" in l][0]
     assert "dispatches=     2" in line and "200.0" in line
+
+
+def test_trace_summary_concurrency(tmp_path):
+    """Kernels A [0, 4) and B [2, 6) ms overlap for 2 ms, then C [10, 11) ms
+    runs alone: 9 ms of kernel time while the device was busy 7 ms, so the
+    mean concurrency is 9/7 = 1.29 and the device is busy 7/11 of the span."""
+    ms = 1_000_000
+    rows = ["Kernel_Name,Start_Timestamp,End_Timestamp",
+            f'"gb::a(int)",{0},{4 * ms}',
+            f'"gb::b(int)",{2 * ms},{6 * ms}',
+            f'"gb::a(int)",{10 * ms},{11 * ms}']
+    (tmp_path / "x_kernel_trace.csv").write_text("\n".join(rows) + "\n")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--trace-summary",
+                        str(tmp_path)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    out = r.stdout
+    assert "3 kernels over 0.011 s, 0.009 s of kernel time" in out
+    assert "device busy 0.007 s (63.6 % of the span), mean concurrency 1.29" in out
+    a = [l for l in out.splitlines() if "gb::a" in l][0]
+    assert "calls=       2" in a and "total=      5.00 ms" in a
