@@ -658,6 +658,7 @@ __global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint3
     __shared__ WgBuckets q;
     __shared__ unsigned long long s_min[kRWaves][kWave];
     __shared__ uint32_t s_b;
+    __shared__ unsigned long long s_packed;
     const int l = lane_id();
     const uint32_t bprev = a.ctl[(j + 1) & 1u];
     const uint32_t st = a.ctl[4 + ((j + 1) & 1u)];
@@ -666,30 +667,38 @@ __global__ __launch_bounds__(kRBlock, 8) void wbfs_step_kernel(WbfsArgs a, uint3
     if (threadIdx.x < 64) {
         // nextBucket: smallest non-empty slot after the previous bucket (or
         // the previous bucket again when its dense step still has to pull)
+        // the found slot's (count, degree sum) comes from the same load;
+        // nothing writes slot b while b is current, so it is the value every
+        // workgroup sees
         uint32_t b = kDone;
+        unsigned long long pk = 0ull;
         if (pull) {
             b = bprev;
+            pk = *slot_counter(a, b & (a.NB - 1));
         } else if (bprev != kDone && !over) {
             for (uint32_t k0 = 1; k0 < a.NB; k0 += 64) {
                 const uint32_t k = k0 + (uint32_t)l;
-                const bool ne =
-                    k < a.NB && (*slot_counter(a, (bprev + k) & (a.NB - 1)) >> 32) != 0;
-                const uint64_t mk = ballot(ne);
+                const unsigned long long cv =
+                    k < a.NB ? *slot_counter(a, (bprev + k) & (a.NB - 1)) : 0ull;
+                const uint64_t mk = ballot((cv >> 32) != 0ull);
                 if (mk) {
-                    b = bprev + k0 + (uint32_t)first_lane(mk);
+                    const int fl = first_lane(mk);
+                    b = bprev + k0 + (uint32_t)fl;
+                    pk = shfl64(cv, fl);
                     break;
                 }
             }
         }
         if (l == 0) {
             s_b = b;
+            s_packed = pk;
             q.cnt = 0;
         }
     }
     __syncthreads();
     const uint32_t b = s_b;
     const uint32_t slot = b & (a.NB - 1);
-    const unsigned long long packed = b == kDone ? 0ull : *slot_counter(a, slot);
+    const unsigned long long packed = s_packed;
     const uint32_t cnt = (uint32_t)(packed >> 32);
     const uint32_t E = (uint32_t)packed;
     // every workgroup reads the same (b, cnt, E): a pending pull is decided
