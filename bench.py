@@ -682,16 +682,27 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         # library's defaults), not the BFS ones
         wopts = tuned_opts(gb, Gw, g, srcs[0], "wbfs")
         extra["wbfs_rmat24_opts"] = wopts
-        tot_e, tot_t = 0, 0.0
-        for s in srcs[:4]:
-            d, p = gb.wbfs(Gw, s)
+        # every one of the 16 sources: GTEPS, buckets, and the fraction of
+        # the HBM roofline by the byte model of a weighted search (8 bytes
+        # per list entry of the reached component, neighbour and weight,
+        # plus 24 per vertex for init and finalize)
+        tot_e, tot_t, nb = 0, 0.0, 0
+        for s in srcs:
+            d, p, st = gb.wbfs(Gw, s, opts=wopts, stats=True)
             e = int(deg[gb.as_u32(d) != 0xFFFFFFFF].sum()) // 2
             t = timed(lambda: gb.wbfs(Gw, s, opts=wopts), reps=2)
             tot_e += e
             tot_t += t
+            nb += st["rounds"]
+        ns = len(srcs)
+        extra["wbfs_rmat24_sources"] = ns
         extra["wbfs_rmat24_gteps"] = round(tot_e / tot_t / 1e9, 2)
-        extra["wbfs_rmat24_ms"] = round(tot_t * 1e3 / 4, 3)
-        log(f"wBFS rmat: {extra['wbfs_rmat24_gteps']} GTEPS, {extra['wbfs_rmat24_ms']} ms/source")
+        extra["wbfs_rmat24_ms"] = round(tot_t * 1e3 / ns, 3)
+        extra["wbfs_rmat24_buckets"] = round(nb / ns, 1)
+        extra["wbfs_rmat24_frac_model"] = round((16 * tot_e + 24 * g.n * ns) / tot_t / 8e12, 4)
+        log(f"wBFS rmat: {extra['wbfs_rmat24_gteps']} GTEPS, {extra['wbfs_rmat24_ms']} ms/source "
+            f"over {ns} sources, {nb / ns:.1f} buckets, model fraction "
+            f"{extra['wbfs_rmat24_frac_model']}")
         # general-weight SSSP (Bellman-Ford rounds) and widest path on the
         # same weighted graph and sources (edges of the reached component,
         # as for wBFS)
@@ -772,12 +783,24 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         topt_b = tuned_opts(gb, T, tg, ts, "bfs") or user_opts
         topt_w = tuned_opts(gb, T, tg, ts, "wbfs")
         tt = timed(lambda: gb.bfs(T, ts, opts=topt_b), reps=2)
-        tw = timed(lambda: gb.wbfs(T, ts, opts=topt_w), reps=1)
+        # weighted BFS from 16 seeded sources (every vertex is reached)
+        t16 = [int(x) for x in gg.sources(tg, 16, seed=3)]
+        tw, nb = 0.0, 0
+        for s in t16:
+            _, _, st = gb.wbfs(T, s, opts=topt_w, stats=True)
+            nb += st["rounds"]
+            tw += timed(lambda: gb.wbfs(T, s, opts=topt_w), reps=1)
+        tw /= len(t16)
         extra["torus256_opts"] = {"bfs": topt_b, "wbfs": topt_w}
         extra["torus256_bfs_ms"] = round(tt * 1e3, 3)
         extra["torus256_bfs_gteps"] = round(tg.m / 2 / tt / 1e9, 3)
+        extra["torus256_wbfs_sources"] = len(t16)
         extra["torus256_wbfs_ms"] = round(tw * 1e3, 3)
-        log(f"torus: BFS {extra['torus256_bfs_ms']} ms, wBFS {extra['torus256_wbfs_ms']} ms")
+        extra["torus256_wbfs_gteps"] = round(tg.m / 2 / tw / 1e9, 3)
+        extra["torus256_wbfs_buckets"] = round(nb / len(t16), 1)
+        extra["torus256_wbfs_frac_model"] = round((8 * tg.m + 24 * tg.n) / tw / 8e12, 4)
+        log(f"torus: BFS {extra['torus256_bfs_ms']} ms, wBFS {extra['torus256_wbfs_ms']} ms per "
+            f"source over {len(t16)} sources ({nb / len(t16):.0f} buckets)")
         # (library defaults: the BFS-tuned options would set the direction
         # threshold the relaxation rounds choose for themselves)
         tbf = timed(lambda: gb.bellman_ford(T, ts), reps=1)
