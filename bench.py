@@ -674,6 +674,44 @@ def timed(fn, reps=3):
 def run_extras(g, G, srcs, gg, gb, torch, user_opts):
     extra = {}
     deg = g.degrees()
+    # RMAT scale 16: one BFS from the first seeded source, median of 100
+    # calls after 5 warm-ups (HIP events around each call); the whole graph
+    # fits in L2 and the Infinity Cache, so its roofline fraction (byte
+    # model over the call's time) is context, not a target
+    try:
+        g16 = gg.rmat(16, seed=1)
+        G16 = gb.Graph.from_csr(g16, validate=False, with_weights=False)
+        s16 = int(gg.sources(g16, 1, seed=3)[0])
+        d16 = torch.empty(g16.n, dtype=torch.int32, device="cuda")
+        p16 = torch.empty(g16.n, dtype=torch.int32, device="cuda")
+        o16 = tuned_opts(gb, G16, g16, s16, "bfs") or {}
+        extra["rmat16_opts"] = o16
+        _, _, st16 = gb.bfs(G16, s16, dist=d16, parent=p16, opts=o16, stats=True)
+        dn, pn = d16.cpu().numpy(), p16.cpu().numpy()
+        he16 = int(g16.degrees()[dn != 2**31 - 1].sum()) // 2
+        b16, _ = bfs_bytes(g16, edge_keys(g16), dn, pn, G16.bfs_log())
+        stream = torch.cuda.current_stream()
+        for _ in range(5):
+            gb.bfs(G16, s16, dist=d16, parent=p16, opts=o16)
+        ts = []
+        for _ in range(100):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            gb.bfs(G16, s16, dist=d16, parent=p16, opts=o16)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms16 = float(np.median(ts))
+        extra["rmat16_bfs_ms"] = round(ms16, 4)
+        extra["rmat16_bfs_gteps"] = round(he16 / (ms16 * 1e-3) / 1e9, 2)
+        extra["rmat16_bfs_rounds"] = st16["rounds"]
+        extra["rmat16_bfs_frac_model"] = round(b16 / (ms16 * 1e-3) / 8e12, 4)
+        log(f"BFS rmat16: {ms16 * 1e3:.1f} us (median of 100), {extra['rmat16_bfs_gteps']} GTEPS, "
+            f"{st16['rounds']} rounds, model fraction {extra['rmat16_bfs_frac_model']}")
+        del G16
+    except Exception as ex:  # noqa: BLE001 - extras must not hide the headline
+        extra["error_rmat16"] = repr(ex)[:300]
     # weighted BFS on the same graph, w in [1, 24)
     try:
         w = gg.weights(g, 24, seed=2)
@@ -761,10 +799,19 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         # batched: 64 sources in one call vs one at a time
         s64 = [int(x) for x in gg.sources(g, 64, seed=3)]
         tb = timed(lambda: gb.bfs_multi(G, s64), reps=2)
+        D0, P0 = gb.bfs_multi(G, s64)
+        D1, P1 = gb.bfs_multi(G, s64, opts={"persistent": 1})
+        same = bool(torch.equal(D0, D1)) and bool(torch.equal(P0, P1))
+        del D1, P1
+        tp = timed(lambda: gb.bfs_multi(G, s64, dist=D0, parent=P0, opts={"persistent": 1}),
+                   reps=2)
+        del D0, P0
         t1 = timed(lambda: [gb.bfs(G, s) for s in s64[:16]], reps=1) * 4
         extra["batched64_qps"] = round(64 / tb, 1)
+        extra["batched64_persistent_qps"] = round(64 / tp, 1) if same else None
         extra["single_qps"] = round(64 / t1, 1)
-        log(f"batched 64: {extra['batched64_qps']} q/s vs one-at-a-time {extra['single_qps']} q/s")
+        log(f"batched 64: {extra['batched64_qps']} q/s ({extra['batched64_persistent_qps']} as one "
+            f"persistent launch) vs one-at-a-time {extra['single_qps']} q/s")
         # the oracle on every host core: independent BFS queries of the
         # batch, one per thread
         import oracle
@@ -852,10 +899,18 @@ def run_uneven_batch(gg, gb):
             qg.append(Gs[i])
             qs.append(int(s))
     tb = timed(lambda: gb.bfs_batch(qg, qs), reps=2)
+    # the same batch as one persistent launch (every round of every group
+    # behind grid barriers), checked equal to the default form
+    D0, P0 = gb.bfs_batch(qg, qs)
+    D1, P1 = gb.bfs_batch(qg, qs, opts={"persistent": 1})
+    same = all(bool((a == b).all()) for a, b in zip(D0 + P0, D1 + P1))
+    tp = timed(lambda: gb.bfs_batch(qg, qs, opts={"persistent": 1}), reps=2)
     t1 = timed(lambda: [gb.bfs(Gq, s) for Gq, s in zip(qg, qs)], reps=2)
     out = {"uneven256_batched_qps": round(len(qs) / tb, 1),
+           "uneven256_persistent_qps": round(len(qs) / tp, 1) if same else None,
            "uneven256_single_qps": round(len(qs) / t1, 1)}
-    log(f"uneven batch of 256 over RMAT 12..20: {out['uneven256_batched_qps']} q/s batched vs "
+    log(f"uneven batch of 256 over RMAT 12..20: {out['uneven256_batched_qps']} q/s batched "
+        f"({out['uneven256_persistent_qps']} as one persistent launch) vs "
         f"{out['uneven256_single_qps']} q/s one at a time")
     for G_ in Gs:
         G_.free()

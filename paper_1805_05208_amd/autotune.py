@@ -29,6 +29,18 @@ BFS_SPACE = {
     "rounds_per_sync": [1, 2, 3, 4, 6],
     "beta": [-1, 8, 24, 64],
 }
+
+
+def bfs_space(n: int) -> Dict[str, Sequence[int]]:
+    """The BFS space for a graph of n vertices: on small graphs (at most 2^18
+    vertices) a launch of hundreds of workgroups is mostly dispatch, so the
+    grid also tries 8 to 32 workgroups."""
+    sp = dict(BFS_SPACE)
+    if n <= (1 << 18):
+        sp["grid"] = [8, 16, 32] + GRID_WIDE
+    return sp
+
+
 WBFS_SPACE = {
     "tau": [5, 7, 10, 14, 20],
     "wave_chunk": [64, 128, 256],
@@ -127,7 +139,7 @@ def tune_bfs(G, srcs: List[int], reps: int = 3, budget_s: float = 60.0, passes: 
                 return None
         return _median_time(lambda: [gb.bfs(G, s, opts=opts) for s in srcs], reps)
 
-    res = coordinate_descent(space or BFS_SPACE, dict(DEFAULTS), cost, passes, budget_s, verbose)
+    res = coordinate_descent(space or bfs_space(G.n), dict(DEFAULTS), cost, passes, budget_s, verbose)
     res["default_cost"] = cost(dict(DEFAULTS))
     res["signature"] = signature(G.n, G.m, max_degree, st["rounds"])
     res["kind"] = "bfs"

@@ -42,3 +42,10 @@ def test_descent_budget_and_signature(tmp_path):
     assert autotune.lookup(str(path), sig, "bfs") == {"tau": 10}
     assert autotune.lookup(str(path), sig, "wbfs") is None
     assert json.load(open(path))[sig]["bfs"]["seconds"] == 0.1
+
+
+def test_small_graphs_try_small_grids():
+    from paper_1805_05208_amd import autotune
+    assert autotune.bfs_space(1 << 16)["grid"][:3] == [8, 16, 32]
+    assert autotune.bfs_space(1 << 24)["grid"] == autotune.GRID_WIDE
+    assert 20 in autotune.bfs_space(1 << 16)["tau"]

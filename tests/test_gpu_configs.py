@@ -87,9 +87,11 @@ def test_config1_rmat16_bfs(gb):
     G = gb.Graph.from_csr(g, with_weights=False)
     srcs = [int(s) for s in gg.sources(g, 16, seed=3)]
     exp = oracle_map(oracle.bfs, [(g, s) for s in srcs])
-    for s, (od, op) in zip(srcs, exp):
-        d, p = gb.bfs(G, s)
-        assert_same(d.cpu().numpy(), p.cpu().numpy(), od, op, f"rmat16 src={s}")
+    # the library defaults and the tuned options the benchmark times
+    for opts in (None, tuned(g, "bfs")):
+        for s, (od, op) in zip(srcs, exp):
+            d, p = gb.bfs(G, s, opts=opts)
+            assert_same(d.cpu().numpy(), p.cpu().numpy(), od, op, f"rmat16 src={s} opts={opts}")
     G.free()
 
 
