@@ -121,7 +121,9 @@ typedef struct {
     double kernel_ms;        /* sum of traversal kernel times (profile = 1)    */
     double wall_ms;          /* host wall time of the call                     */
     int32_t retries;         /* wBFS reruns after a bucket overflow            */
-    int32_t reserved[7];
+    int32_t bucket_peak;     /* wBFS: entries of the fullest bucket (what the
+                                bucket capacity must hold); 0 if unknown      */
+    int32_t reserved[6];
 } gbgpu_stats;
 
 /* Register a CSR graph that already lives in device memory.

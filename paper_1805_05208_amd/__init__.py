@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
         ("pull_rounds", ctypes.c_int32), ("launches", ctypes.c_int32),
         ("reached", ctypes.c_int64), ("edges_examined", ctypes.c_int64),
         ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
-        ("retries", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("retries", ctypes.c_int32), ("bucket_peak", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
     def as_dict(self):

@@ -179,4 +179,32 @@ inline bool sched_requeue_overflow(std::deque<PendingQ>& pending, const SchedEnv
     return true;
 }
 
+// The learned bucket capacity of a graph coming back down.  Every weighted
+// query on the graph that finished without overflow reports the fill of its
+// fullest bucket (`peak`; 0 when unknown).  Once kCapWindow such reports
+// have been seen, a learned capacity at least four times the largest of
+// them drops to twice that largest fill, or back to the default (0) when
+// that is not above default_cap; then a new window starts.  One outlier
+// source that forced the capacity up thus stops inflating every later
+// query's footprint, and a graph whose queries keep filling their buckets
+// keeps its capacity.
+constexpr uint32_t kCapWindow = 32;
+
+struct CapWindow {
+    uint32_t peak_max = 0;
+    uint32_t n = 0;
+};
+
+inline void sched_note_peak(uint32_t& learned, CapWindow& w, uint32_t peak,
+                            uint32_t default_cap) {
+    if (learned == 0 || peak == 0) return;  // nothing learned, or fill unknown
+    w.peak_max = std::max(w.peak_max, peak);
+    if (++w.n < kCapWindow) return;
+    if ((uint64_t)w.peak_max * 4 <= (uint64_t)learned) {
+        const uint64_t c = (uint64_t)w.peak_max * 2;
+        learned = c <= default_cap ? 0u : (uint32_t)c;
+    }
+    w = CapWindow{};
+}
+
 }  // namespace gb

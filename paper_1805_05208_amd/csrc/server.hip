@@ -77,6 +77,7 @@ struct gbgpu_server_s {
     gbgpu_opts opts;
     std::vector<gbgpu_graph> graphs;
     std::vector<uint32_t> wcap;       // per graph: bucket capacity a weighted query needed
+    std::vector<gb::CapWindow> capwin;  // per graph: bucket fills since wcap last changed
     gb::SchedEnv env;                 // admission rule's view of the graphs
     std::mutex mu;
     std::condition_variable cv;       // work available / memory freed / stop
@@ -131,6 +132,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
         void* mem = sv->arena + off;
         gbgpu_graph g = sv->graphs[job[0].q.graph_id];
         int status = GBGPU_OK, rounds = 0, launches = 0;
+        uint32_t peak = 0;  // weighted query without overflow: its fullest bucket
         bool requeue = false;
         uint32_t usedcap = 0;
         if (job.size() > 1) {
@@ -156,7 +158,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
                                       kcap > job.size() ? &hook : nullptr);
         } else if (job[0].q.kind == GBGPU_QUERY_BFS) {
             bfs_ws_attach(w->bws, mem, g->n, g->nwords);
-            gbgpu_stats st;
+            gbgpu_stats st{};
             status = run_bfs_ws(g, w->bws, job[0].q.src, (int32_t*)job[0].q.dist, job[0].q.parent,
                                 sv->opts, &st, w->stream, true, true);  // the arena is reused at once
             rounds = st.rounds;
@@ -165,7 +167,7 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
             const uint32_t NB = wbfs_window(g->maxw, sv->opts.bucket_window);
             const uint32_t C = initial_capacity(g, job[0].cap, sv->opts);
             wbfs_ws_attach(w->wws, mem, g->n, NB, C);
-            gbgpu_stats st;
+            gbgpu_stats st{};
             bool overflow = false;
             status = run_wbfs_ws(g, w->wws, job[0].q.src, (uint32_t*)job[0].q.dist, job[0].q.parent,
                                  sv->opts, &st, w->stream, &overflow);
@@ -174,11 +176,17 @@ static void worker_loop(gbgpu_server sv, Worker* w) {
             if (status == GBGPU_OK && overflow) {
                 requeue = true;
                 usedcap = C;
+            } else if (status == GBGPU_OK) {
+                peak = (uint32_t)std::max(st.bucket_peak, 0);
             }
         }
         lk.lock();
         sv->alloc.release(off, bytes);
         --sv->running;
+        if (peak) {
+            const int32_t gid = job[0].q.graph_id;
+            sched_note_peak(sv->wcap[gid], sv->capwin[gid], peak, initial_capacity(g, 0, sv->opts));
+        }
         if (requeue) {
             // re-queued at the front with twice the buckets; failed when the
             // larger workspace could never be admitted
@@ -316,6 +324,7 @@ int gbgpu_server_add_graph(gbgpu_server sv, gbgpu_graph g, int32_t* graph_id) {
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->graphs.push_back(g);
     sv->wcap.push_back(0u);
+    sv->capwin.push_back(CapWindow{});
     *graph_id = (int32_t)sv->graphs.size() - 1;
     return GBGPU_OK;
 }

@@ -888,6 +888,7 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
             st->kernel_ms = ms;
         }
         const uint32_t* lg = w->hl.h + kHostLogOff;
+        uint32_t peak = 0;
         for (uint32_t i = 0; i < std::min<uint32_t>(steps, (uint32_t)kWLogCap); ++i) {
             if (lg[4 * i + 3] == kModePull) {
                 st->pull_rounds++;
@@ -896,7 +897,10 @@ int run_wbfs_ws(gbgpu_graph g, WbfsWs* w, int32_t src, uint32_t* dist, int32_t* 
             st->rounds++;
             if (lg[4 * i + 3] == kModePush) st->push_rounds++;
             st->edges_examined += lg[4 * i + 2];
+            peak = std::max(peak, lg[4 * i + 1]);
         }
+        // the fill of every bucket is known only when every step was logged
+        st->bucket_peak = steps <= (uint32_t)kWLogCap ? (int32_t)peak : 0;
         st->launches = (int32_t)launches;
         st->wall_ms = now_ms() - t0;
     }

@@ -238,6 +238,41 @@ static void test_arena_random() {
     CHECK(a.largest() == units * 256);
 }
 
+// The learned capacity comes back down only after a full window of
+// reports, only when it is at least four times the window's largest fill,
+// and never below the default; unknown fills and the default are ignored.
+static void test_learned_capacity_decay() {
+    const uint32_t dflt = 1000;
+    {
+        uint32_t learned = 0;  // default: nothing to lower
+        CapWindow w;
+        for (uint32_t i = 0; i < 2 * kCapWindow; ++i) sched_note_peak(learned, w, 10, dflt);
+        CHECK(learned == 0 && w.n == 0);
+    }
+    {
+        uint32_t learned = 16000;  // an outlier grew it; later fills stay <= 3000
+        CapWindow w;
+        for (uint32_t i = 0; i + 1 < kCapWindow; ++i) sched_note_peak(learned, w, 500 + i * 80, dflt);
+        CHECK(learned == 16000 && w.n == kCapWindow - 1);  // window not full yet
+        sched_note_peak(learned, w, 0, dflt);               // unknown fill: not counted
+        CHECK(learned == 16000 && w.n == kCapWindow - 1);
+        sched_note_peak(learned, w, 3000, dflt);
+        CHECK(learned == 6000 && w.n == 0);                  // twice the largest fill
+    }
+    {
+        uint32_t learned = 16000;  // fills above a quarter of it: kept
+        CapWindow w;
+        for (uint32_t i = 0; i < kCapWindow; ++i) sched_note_peak(learned, w, i == 7 ? 4001 : 100, dflt);
+        CHECK(learned == 16000 && w.n == 0);
+    }
+    {
+        uint32_t learned = 4000;  // twice the largest fill is below the default
+        CapWindow w;
+        for (uint32_t i = 0; i < kCapWindow; ++i) sched_note_peak(learned, w, 300, dflt);
+        CHECK(learned == 0);
+    }
+}
+
 int main() {
     test_oldest_first_alone();
     test_packs_same_graph_bfs_in_order();
@@ -246,6 +281,7 @@ int main() {
     test_head_of_line_waits_for_memory();
     test_memory_accounting_over_a_run();
     test_learned_capacity_and_requeue();
+    test_learned_capacity_decay();
     test_arena_random();
     if (failures) {
         printf("%d checks failed\n", failures);

@@ -120,6 +120,21 @@ def test_wbfs_forced_directions_identical(gb, rmat16, force):
         assert_wbfs(gb, g, G, int(s), opts={"force_direction": force}, tag=f"wforce{force}")
 
 
+def test_wbfs_bucket_peak(gb, rmat16):
+    """bucket_peak is the largest entry count of the buckets the search
+    processed (their fill, what the capacity must hold): the largest count
+    in the step log, and never above the capacity of a run that did not
+    have to grow it."""
+    g, G = rmat16
+    for s in (int(x) for x in gg.sources(g, 3, seed=5)):
+        for opts in (None, {"bucket_capacity": 64}):
+            _, _, st = gb.wbfs(G, s, opts=opts, stats=True)
+            lg = G.wbfs_log()
+            assert st["bucket_peak"] == int(lg[lg[:, 3] != 2, 1].max()) > 0
+            if opts:
+                assert st["bucket_peak"] <= min(g.n, 64 * 2 ** st["retries"]), st
+
+
 def test_wbfs_dense_steps_in_auto_mode(gb, rmat16):
     """The default threshold sends the heavy buckets of an RMAT graph dense;
     every dense bucket takes a marking launch followed by a pull launch of

@@ -132,13 +132,21 @@ def test_server_learned_capacity_and_batching_rule(gb, graphs):
     assert alone[0]["batch"] == 1
     packed = run(gb.QUERY_BFS, srcs)          # shallow and small: packed together
     assert max(r["batch"] for r in packed) > 1
-    # the queries of one packed run share its start time, and their number
-    # is the batch size each of them reports
+    # the queries that started a packed run share its start time and report
+    # its size: they plus the queries that joined it at a round boundary
+    # (join_round > 0, each with the time it joined as its start)
     by_start = {}
+    joined = [r for r in packed if r["join_round"] > 0]
     for r in packed:
-        by_start.setdefault(r["t_start_ns"], []).append(r["batch"])
+        if r["join_round"] == 0:
+            by_start.setdefault(r["t_start_ns"], []).append(r["batch"])
+    extra = 0
     for bs in by_start.values():
-        assert all(b == len(bs) for b in bs), by_start
+        assert len(set(bs)) == 1 and bs[0] >= len(bs), by_start
+        extra += bs[0] - len(bs)
+    assert extra == len(joined), (by_start, joined)
+    sizes = {bs[0] for bs in by_start.values()}
+    assert all(r["batch"] in sizes for r in joined), (by_start, joined)
     sv.close()
     G.free()
 
