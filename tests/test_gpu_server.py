@@ -130,7 +130,27 @@ def test_server_learned_capacity_and_batching_rule(gb, graphs):
     run(gb.QUERY_WBFS, srcs[1:4])
     alone = run(gb.QUERY_BFS, srcs[:1])       # depth unknown: alone
     assert alone[0]["batch"] == 1
-    packed = run(gb.QUERY_BFS, srcs)          # shallow and small: packed together
+    sv.close()
+    # shallow and small, the graph's BFS queries are now packed: they arrive
+    # while the one worker of a second server is busy with a long weighted
+    # query (a 40^3 torus, about 120 buckets), so they wait together
+    t = gg.torus3d(40).with_weights(8, seed=1)
+    T = gb.Graph.from_csr(t)
+    sv = gb.Server(arena_bytes=1 << 30, max_inflight=1)
+    gid, tid = sv.add_graph(G), sv.add_graph(T)
+    tb = [torch.empty(t.n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    outs = [(torch.empty(g.n, dtype=torch.int32, device="cuda"),
+             torch.empty(g.n, dtype=torch.int32, device="cuda")) for _ in srcs]
+    torch.cuda.synchronize()
+    blocker = sv.submit(tid, gb.QUERY_WBFS, 0, tb[0], tb[1])
+    tickets = [sv.submit(gid, gb.QUERY_BFS, s, d, p) for s, (d, p) in zip(srcs, outs)]
+    res = wait(sv, [blocker] + tickets)
+    assert res[blocker]["status"] == gb.OK
+    packed = [res[x] for x in tickets]
+    for r, s, (d, p) in zip(packed, srcs, outs):
+        assert r["status"] == gb.OK
+        od, op = oracle.bfs(g, s)
+        assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op), s
     assert max(r["batch"] for r in packed) > 1
     # the queries that started a packed run share its start time and report
     # its size: they plus the queries that joined it at a round boundary
@@ -149,6 +169,7 @@ def test_server_learned_capacity_and_batching_rule(gb, graphs):
     assert all(r["batch"] in sizes for r in joined), (by_start, joined)
     sv.close()
     G.free()
+    T.free()
 
 
 def test_server_errors(gb, graphs):
