@@ -76,6 +76,7 @@ def coordinate_descent(space: Dict[str, Sequence[int]], start: Dict[str, int],
     best_cost = cost(best)
     if best_cost is None:
         raise RuntimeError("the starting configuration was rejected")
+    start_cost = best_cost
     tried = {tuple(sorted(best.items())): best_cost}
     rejected = []
     for _ in range(passes):
@@ -83,8 +84,8 @@ def coordinate_descent(space: Dict[str, Sequence[int]], start: Dict[str, int],
         for knob, values in space.items():
             for val in values:
                 if time.time() - t0 > budget_s:
-                    return {"opts": best, "cost": best_cost, "tried": len(tried),
-                            "rejected": rejected, "timed_out": True}
+                    return {"opts": best, "cost": best_cost, "start_cost": start_cost,
+                            "tried": len(tried), "rejected": rejected, "timed_out": True}
                 cand = dict(best)
                 cand[knob] = val
                 key = tuple(sorted(cand.items()))
@@ -102,8 +103,8 @@ def coordinate_descent(space: Dict[str, Sequence[int]], start: Dict[str, int],
                     best, best_cost, improved = cand, c, True
         if not improved:
             break
-    return {"opts": best, "cost": best_cost, "tried": len(tried), "rejected": rejected,
-            "timed_out": False}
+    return {"opts": best, "cost": best_cost, "start_cost": start_cost, "tried": len(tried),
+            "rejected": rejected, "timed_out": False}
 
 
 def signature(n: int, m: int, max_degree: int, rounds: int) -> str:

@@ -49,3 +49,13 @@ def test_small_graphs_try_small_grids():
     assert autotune.bfs_space(1 << 16)["grid"][:3] == [8, 16, 32]
     assert autotune.bfs_space(1 << 24)["grid"] == autotune.GRID_WIDE
     assert 20 in autotune.bfs_space(1 << 16)["tau"]
+
+
+def test_search_never_ends_slower_than_its_start():
+    from paper_1805_05208_amd import autotune
+    costs = {5: 3.0, 10: 1.0, 20: 2.0}
+    r = autotune.coordinate_descent({"tau": [5, 10, 20]}, {"tau": 20},
+                                    lambda o: costs[o["tau"]], passes=2, budget_s=10)
+    assert r["opts"] == {"tau": 10} and r["cost"] == 1.0 and r["start_cost"] == 2.0
+    r = autotune.coordinate_descent({"tau": [5]}, {"tau": 20}, lambda o: costs[o["tau"]])
+    assert r["opts"] == {"tau": 20} and r["cost"] == r["start_cost"] == 2.0
