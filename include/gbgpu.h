@@ -193,9 +193,11 @@ int gbgpu_bfs_many(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist,
  * and round log live in a library-owned static device array of 64 MiB per
  * device (held from the library's first use on that device until the
  * process ends), so the graph's workspace is never allocated.
- *   n limit   at most about 3.9 million vertices: the workspace takes
- *             16 n + 0.4 n / 8 bytes plus about 170 KB of control words
- *   other arguments as gbgpu_bfs; st->kernel_ms is always 0 (no events)
+ *   n limit   at most about 4.05 million vertices: the workspace takes
+ *             16.5 n bytes (four 4-byte vertex arrays and four bitmaps) plus
+ *             about 170 KB of control words and round log
+ *   other arguments as gbgpu_bfs; st->kernel_ms is always 0 (no events);
+ *             o->persistent is ignored (one launch per round)
  * The host checks for the end of the search by copying four progress words
  * back after every max(8, rounds_per_sync) round launches and synchronising
  * the stream, so the call returns with the stream drained.  Calls for one
