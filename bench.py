@@ -203,6 +203,20 @@ def main():
     ap.add_argument("--trace-summary", type=str, default="",
                     help="print per-kernel totals and device concurrency of a rocprofv3 "
                          "--kernel-trace csv directory and exit")
+    ap.add_argument("--segments", type=str, default="",
+                    help="per-dispatch durations (kernel trace) or counter values (--pmc run) "
+                         "of a rocprofv3 csv directory, in searches that start at --start; "
+                         "print and exit")
+    ap.add_argument("--start", type=str, default="bfs_init_kernel",
+                    help="kernel that begins each search (with --segments)")
+    ap.add_argument("--kernel", type=str, default="",
+                    help="only dispatches of this kernel (with --segments)")
+    ap.add_argument("--segment", type=int, default=-1,
+                    help="print the dispatches of this search only (with --segments)")
+    ap.add_argument("--counter", type=str, default="",
+                    help="only this counter of a --pmc run (with --segments)")
+    ap.add_argument("--step-log", type=str, default="",
+                    help="a --only wbfs log: totals by kind of step (with --segments)")
     ap.add_argument("--serving-queries", type=int, default=2000,
                     help="Poisson arrivals per offered load in the serving section")
     ap.add_argument("--no-tuned", action="store_true",
@@ -217,6 +231,10 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.segments:
+        segments(args.segments, args.start, args.kernel, args.segment, args.step_log,
+                 args.counter)
         return
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -644,6 +662,62 @@ def trace_summary(path, window_s=1.0):
     for i in range(nwin):
         if busy[i]:
             print(f"{i * window_s:6.0f}  {100.0 * busy[i] / w:5.1f}  {work[i] / busy[i]:6.2f}")
+
+
+def segments(path, start, kernel="", which=-1, step_log="", counter=""):
+    """Dispatches of a rocprofv3 run in Dispatch_Id order, cut into searches
+    at each dispatch of `start`: per dispatch its duration in us (a
+    kernel_trace csv) or its counter value summed over the counters and
+    dimensions collected, or of `counter` alone (a counter_collection csv),
+    kernel names without arguments.  With a step log (the JSON line of `bench.py --only wbfs`,
+    whose step_logs come in search order from the first search), the
+    weighted-BFS step dispatches of each logged search are totalled by kind
+    of step (push / mark / pull)."""
+    import csv
+    import glob
+    from collections import OrderedDict
+    rows = []
+    for pat in ("*kernel_trace.csv", "*counter_collection.csv"):
+        for f in glob.glob(os.path.join(path, "**", pat), recursive=True):
+            with open(f) as fh:
+                rows += [(pat, r) for r in csv.DictReader(fh)]
+    disp = OrderedDict()
+    for pat, r in sorted(rows, key=lambda pr: int(pr[1]["Dispatch_Id"])):
+        d = int(r["Dispatch_Id"])
+        name = r["Kernel_Name"].split("(")[0]
+        if pat.startswith("*kernel"):
+            disp[d] = [name, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3]
+        elif not counter or r["Counter_Name"] == counter:
+            disp.setdefault(d, [name, 0.0])[1] += float(r["Counter_Value"])
+    segs = []
+    for name, v in disp.values():
+        if start in name:
+            segs.append([])
+        if segs and (not kernel or kernel in name):
+            segs[-1].append((name, v))
+    unit = "us" if rows and rows[0][0].startswith("*kernel") else "counter"
+    print(f"{len(segs)} searches starting at {start}; values in {unit}")
+    for i, sg in enumerate(segs):
+        if which >= 0 and i != which:
+            continue
+        tot = sum(v for _, v in sg)
+        print(f"search {i}: {len(sg)} dispatches, total {tot:.1f}")
+        if which >= 0:
+            for j, (name, v) in enumerate(sg):
+                print(f"  {j:5d} {name:40s} {v:14.1f}")
+    if step_log:
+        with open(step_log) as fh:
+            line = [x for x in fh if x.startswith('{"metric"')][-1]
+        logs = json.loads(line)["step_logs"]
+        for i, (src, lg) in enumerate(logs.items()):
+            steps = [v for name, v in segs[i] if "wbfs_step_kernel" in name][:len(lg)]
+            tot = {}
+            for (_b, _c, _e, mode), v in zip(lg, steps):
+                k = ("push", "mark", "pull")[mode]
+                n, x = tot.get(k, (0, 0.0))
+                tot[k] = (n + 1, x + v)
+            print(f"source {src}: {len(lg)} steps; " + ", ".join(
+                f"{k} {n} steps {x:.1f}" for k, (n, x) in tot.items()))
 
 
 TUNED = os.path.join(ROOT, "paper_1805_05208_amd", "tuned.json")

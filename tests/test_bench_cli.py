@@ -48,3 +48,29 @@ def test_trace_summary_concurrency(tmp_path):
     assert "device busy 0.007 s (63.6 % of the span), mean concurrency 1.29" in out
     a = [l for l in out.splitlines() if "gb::a" in l][0]
     assert "calls=       2" in a and "total=      5.00 ms" in a
+
+
+def test_segments_split_searches_and_total_steps(tmp_path):
+    """Dispatches cut at each start kernel; a step log totals the weighted
+    step dispatches of each logged search by kind."""
+    rows = ["Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp"]
+    t = 0
+    seq = ["gb::wbfs_init_kernel", "gb::wbfs_step_kernel", "gb::wbfs_step_kernel",
+           "gb::wbfs_step_kernel", "gb::wbfs_init_kernel", "gb::wbfs_step_kernel"]
+    for i, k in enumerate(seq):
+        rows.append(f'{i + 1},"{k}(int)",{t},{t + 1000 * (i + 1)}')
+        t += 100000
+    (tmp_path / "x_kernel_trace.csv").write_text("\n".join(rows) + "\n")
+    log = tmp_path / "run.log"
+    log.write_text('{"metric": "wbfs_section", "step_logs": {"7": [[0, 1, 2, 0], [3, 4, 5, 1], '
+                   '[3, 4, 5, 2]], "9": [[0, 1, 1, 0]]}}\n')
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--segments", str(tmp_path),
+                        "--start", "wbfs_init_kernel", "--kernel", "wbfs_step_kernel",
+                        "--step-log", str(log), "--segment", "0"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    out = r.stdout
+    assert "2 searches starting at wbfs_init_kernel; values in us" in out
+    assert "search 0: 3 dispatches, total 9.0" in out      # 2 + 3 + 4 us
+    assert "source 7: 3 steps; push 1 steps 2.0, mark 1 steps 3.0, pull 1 steps 4.0" in out
+    assert "source 9: 1 steps; push 1 steps 6.0" in out
