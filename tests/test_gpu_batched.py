@@ -196,3 +196,15 @@ def test_single_launch_uneven_batch_and_small_graphs(gb):
         srcs = np.arange(min(g.n, 70), dtype=np.int32) % g.n
         D, P = gb.bfs_multi(G, srcs, opts={"persistent": 1})
         check_rows(g, srcs, D, P, tag=f"single launch {g.name}")
+
+
+def test_single_launch_batches_many_workgroups(gb):
+    g = gg.rmat(16, seed=2)
+    G = gb.Graph.from_csr(g, with_weights=False)
+    srcs = gg.sources(g, 100, seed=6)
+    D, P, st = gb.bfs_multi(G, srcs, opts={"persistent": 1, "grid": 512}, stats=True)
+    check_rows(g, srcs[::9], D[::9], P[::9], tag="single launch grid 512")
+    D2, P2 = gb.bfs_multi(G, srcs)
+    assert torch.equal(D, D2) and torch.equal(P, P2)
+    assert st["launches"] == 1
+    G.free()

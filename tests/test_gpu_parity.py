@@ -338,3 +338,26 @@ def test_default_is_one_launch_per_round(gb):
         od, op = oracle.bfs(g, s)
         assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op)
     G.free()
+
+
+def test_single_launch_many_workgroups_per_die(gb):
+    """The single-launch form with hundreds of workgroups (dozens per die,
+    so the die leaders' write-back and every workgroup's acquire carry the
+    rounds), on a deep and on a shallow graph, and from an isolated source
+    and from a degree-1 source."""
+    for g in (gg.torus3d(48), gg.rmat(18, seed=4)):
+        G = gb.Graph.from_csr(g, with_weights=False)
+        deg = g.degrees()
+        srcs = [int(x) for x in gg.sources(g, 2, seed=13)]
+        if (deg == 0).any():
+            srcs.append(int(np.nonzero(deg == 0)[0][0]))
+        if (deg == 1).any():
+            srcs.append(int(np.nonzero(deg == 1)[0][0]))
+        for s in srcs:
+            od, op = oracle.bfs(g, s)
+            for grid in (256, 512):
+                d, p, st = gb.bfs(G, s, opts={"persistent": 1, "grid": grid}, stats=True)
+                assert np.array_equal(d.cpu().numpy(), od), (g.name, s, grid)
+                assert np.array_equal(p.cpu().numpy(), op), (g.name, s, grid)
+                assert st["launches"] == 1, (g.name, s, grid, st)
+        G.free()
