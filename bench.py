@@ -217,6 +217,8 @@ def main():
                     help="only this counter of a --pmc run (with --segments)")
     ap.add_argument("--step-log", type=str, default="",
                     help="a --only wbfs log: totals by kind of step (with --segments)")
+    ap.add_argument("--serving-workers", type=int, default=8,
+                    help="queries the server keeps on the device at once (worker streams)")
     ap.add_argument("--serving-queries", type=int, default=2000,
                     help="Poisson arrivals per offered load in the serving section")
     ap.add_argument("--no-tuned", action="store_true",
@@ -361,7 +363,7 @@ def main():
     if args.only == "serving":
         res = {"metric": "serving_section", "config": {"workload": "six resident graphs"}}
         res.update(run_serving(g, G, gg, gb, torch, nq=args.serving_queries,
-                               cpu=not args.no_cpu))
+                               cpu=not args.no_cpu, workers=args.serving_workers))
         print(json.dumps(res), flush=True)
         return
     if args.only == "connectivity":
@@ -1108,7 +1110,7 @@ class ServedMix:
         return out
 
 
-def run_serving(g, G, gg, gb, torch, nq=2000, cpu=True):
+def run_serving(g, G, gg, gb, torch, nq=2000, cpu=True, workers=8):
     """Poisson arrivals of mixed BFS / weighted BFS queries on the six
     resident graphs, at 0.5x and 0.8x of the saturated rate, every served
     result verified against the standalone call."""
@@ -1129,7 +1131,7 @@ def run_serving(g, G, gg, gb, torch, nq=2000, cpu=True):
         hosts[name] = (h, h.weights)
         log(f"serving graph {name}: n={h.n} m={h.m} loaded in {time.perf_counter() - t:.1f}s")
     # a weighted BFS on RMAT-26 takes ~9 GB of workspace (64 buckets of n/4)
-    sv = gb.Server(arena_bytes=96 << 30, max_inflight=8)
+    sv = gb.Server(arena_bytes=96 << 30, max_inflight=workers)
     ids = [sv.add_graph(GG) for _, _, GG in graphs]
     mix = ServedMix(graphs, sv, ids, gg, gb, torch)
     t = time.perf_counter()
