@@ -573,6 +573,10 @@ __device__ __forceinline__ bool bfs_round(const BfsArgs& a, uint32_t r, WgQueue&
     unsigned long long* qover = a.ctl + 8;
     unsigned long long* tot = a.ctl + 64;  // 4 slots x kSpread x kSpreadStride
     const uint32_t rs = r & 3u;
+    // written by earlier rounds and independent of the totals: loaded with
+    // them, one trip before the workgroup barrier instead of one after it
+    const unsigned long long reached_before = a.ctl[14 + ((r + 1) & 1u)];
+    const unsigned long long qover_r = qover[rs];
     if (threadIdx.x < kWave) {
         const unsigned long long t = spread_sum(tot + (size_t)rs * kSpread * kSpreadStride);
         if (threadIdx.x == 0) s_tot = t;
@@ -599,7 +603,7 @@ __device__ __forceinline__ bool bfs_round(const BfsArgs& a, uint32_t r, WgQueue&
     const uint32_t edges = (uint32_t)packed;
     // vertices of nonzero degree not yet reached after round r: the number
     // reached through round r-1 was left by the previous launch
-    const unsigned long long reached = a.ctl[14 + ((r + 1) & 1u)] + count;
+    const unsigned long long reached = reached_before + count;
     const unsigned long long unvisited = a.nnz > reached ? a.nnz - reached : 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[14 + (r & 1u)] = reached;
     if (count == 0) {
@@ -609,7 +613,7 @@ __device__ __forceinline__ bool bfs_round(const BfsArgs& a, uint32_t r, WgQueue&
         if ((s_prev >> 32) != 0) attach_leaves(a, r, q);
         return true;
     }
-    const bool qvalid = qover[rs] == 0;
+    const bool qvalid = qover_r == 0;
     const bool push = choose_push(a, r, count, edges, qvalid);
 
     uint32_t* Fs[3] = {a.F0, a.F1, a.F2};
