@@ -788,6 +788,58 @@ def run_extras(g, G, srcs, gg, gb, torch, user_opts):
         del G16
     except Exception as ex:  # noqa: BLE001 - extras must not hide the headline
         extra["error_rmat16"] = repr(ex)[:300]
+    # two searches in flight (beside the sequential headline, never instead
+    # of it): a second handle on the same CSR arrays has its own workspace;
+    # two host threads each run half of the 16 sources back to back on a
+    # stream of their own, so one search's small rounds and tail launches
+    # overlap the other's dense rounds
+    try:
+        import threading
+        G2 = gb.Graph(G.offsets, G.nbrs, None, validate=False)
+        he = []
+        for s in srcs:
+            d, _ = gb.bfs(G, s, opts=user_opts)
+            he.append(int(deg[d.cpu().numpy() != 2**31 - 1].sum()) // 2)
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        bufs = [(torch.empty(g.n, dtype=torch.int32, device="cuda"),
+                 torch.empty(g.n, dtype=torch.int32, device="cuda")) for _ in range(2)]
+        lat = [[], []]
+
+        def half(i, record):
+            H = (G, G2)[i]
+            d, p = bufs[i]
+            for s in srcs[i::2]:
+                t = time.perf_counter()
+                gb.bfs(H, s, dist=d, parent=p, opts=user_opts, stream=streams[i])
+                if record:
+                    lat[i].append(time.perf_counter() - t)
+
+        def both(record):
+            th = [threading.Thread(target=half, args=(i, record)) for i in range(2)]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join()
+            torch.cuda.synchronize()
+
+        both(False)
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            both(True)
+        wall = time.perf_counter() - t0
+        # each thread's last search against the same search on its own
+        same = True
+        for i in range(2):
+            d0, p0 = gb.bfs(G, srcs[i::2][-1], opts=user_opts)
+            same &= bool(torch.equal(d0, bufs[i][0])) and bool(torch.equal(p0, bufs[i][1]))
+        extra["bfs_two_in_flight_gteps"] = round(sum(he) * reps / wall / 1e9, 1) if same else None
+        extra["bfs_two_in_flight_ms_per_search"] = round(1e3 * float(np.median(lat[0] + lat[1])), 3)
+        log(f"BFS, two searches in flight: {extra['bfs_two_in_flight_gteps']} GTEPS, "
+            f"{extra['bfs_two_in_flight_ms_per_search']} ms per search (median)")
+        G2.free()
+    except Exception as ex:  # noqa: BLE001 - extras must not hide the headline
+        extra["error_two_in_flight"] = repr(ex)[:300]
     # weighted BFS on the same graph, w in [1, 24)
     try:
         w = gg.weights(g, 24, seed=2)
