@@ -5,7 +5,10 @@
 * the query server's scheduling rules (paper_1805_05208_amd/csrc/admission.h:
   first-fit arena, admission with bit-packing and halving, head-of-line
   waiting for memory, overflow re-queue and learned bucket capacity) with
-  fake graphs and footprints (sched_check.cpp).
+  fake graphs and footprints (sched_check.cpp);
+* the grid-barrier protocol of the single-launch forms
+  (paper_1805_05208_amd/csrc/gridbar_protocol.h), the same code run by
+  threads standing for workgroups on uneven dies (gridbar_model.cpp).
 
 Each driver is compiled here with gcc / g++ and run as a child process; a
 sanitizer report makes it exit non-zero.
@@ -51,3 +54,11 @@ def test_server_scheduling_rules_under_sanitizers(tmp_path):
                          os.path.join(HERE, "sched_check.cpp")],
                         str(tmp_path / "sched_check"))
     assert "scheduler checks passed" in out
+
+
+def test_grid_barrier_protocol_on_threads(tmp_path):
+    out = build_and_run(["g++", "-std=c++17", *SAN, "-pthread",
+                         "-I" + os.path.join(ROOT, "paper_1805_05208_amd", "csrc"),
+                         os.path.join(HERE, "gridbar_model.cpp")],
+                        str(tmp_path / "gridbar_model"))
+    assert "grid barrier model checks passed" in out
