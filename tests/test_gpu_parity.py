@@ -361,3 +361,15 @@ def test_single_launch_many_workgroups_per_die(gb):
                 assert np.array_equal(p.cpu().numpy(), op), (g.name, s, grid)
                 assert st["launches"] == 1, (g.name, s, grid, st)
         G.free()
+
+
+@pytest.mark.parametrize("force", [1, 2, 3])
+def test_single_launch_forced_directions(gb, rmat16, force):
+    """Push-only, pull-only and alternating rounds in one launch give the
+    oracle's outputs, as they do one launch per round."""
+    g, G = rmat16
+    for s in gg.sources(g, 3, seed=17):
+        d, p, st = gb.bfs(G, int(s), opts={"persistent": 1, "force_direction": force}, stats=True)
+        od, op = oracle.bfs(g, int(s))
+        assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(p.cpu().numpy(), op), (force, s)
+        assert st["launches"] == 1
