@@ -9,14 +9,16 @@
 // totals, exactly like the single-source edgeMap switch:
 //   push (sparse): the frontier list (ids + degree prefix) is expanded edge by
 //     edge; for an edge (u, v), the bits of F_r[u] that v has not seen are
-//     OR-ed into F_{r+1}[v] and every such bit j takes atomicMin(parent_j[v], u);
+//     OR-ed into F_{r+1}[v] and every such bit j takes the atomic minimum of
+//     its pair entry with (r + 1, u);
 //   pull (dense): every vertex with unseen bits scans its ascending list; the
 //     first neighbour u that carries bit j in F_r becomes parent_j[v] (a
 //     wavefront prefix-OR finds first contributors when a whole wavefront
 //     scans one list), with early exit once every unseen bit is found.
 // Both rules give parent_j[v] = min{u in N(v) : D_j[u] = D_j[v] - 1}, so each
-// row equals the single-source BFS from source j.  Distances are written when
-// a vertex's bits enter the frontier: D_j[v] = r for the bits of F_r[v].
+// row equals the single-source BFS from source j.  A pair (v, j) is written
+// once, in the round r that finds it, as one 64-bit entry (arrival round
+// r + 1, parent): D_j[v] = r + 1, the round whose frontier holds bit j of v.
 // Groups finish independently; a finished group costs nothing.
 
 #include "common.h"
@@ -50,8 +52,9 @@ struct MsGroupDev {
     uint32_t nplan;
     uint32_t k;                 // capacity: sources the staging holds per vertex
     uint32_t kused;             // sources in the group so far (bits 0 .. kused-1)
-    uint32_t* PS;               // vertex-major parents, PS[v * k + j]
-    uint32_t* DS;               // vertex-major rounds of arrival, DS[v * k + j]
+    // vertex-major pair entries E[v * k + j] = (round of arrival << 32) |
+    // parent, written when the pair is found; ~0 until then
+    unsigned long long* E;
     uint32_t* start;            // round at which source j joined the group (64)
 };
 
@@ -105,13 +108,12 @@ __global__ __launch_bounds__(kBlock) void ms_init_kernel(MsGroupDev* groups, int
         G.F[1][v] = 0ull;
         G.F[2][v] = 0ull;
     }
-    // parents start at "none" so sparse rounds can take atomicMin; distances
-    // need no initialisation (written once per reached pair, and the final
-    // transpose reads them only for reached pairs)
+    // pair entries start at ~0 so that sparse rounds can take atomicMin (the
+    // final transpose reads only reached pairs)
     const int64_t tot = G.n * (int64_t)G.k;
-    uint4* ps4 = (uint4*)G.PS;
-    for (int64_t i = tid; i < tot / 4; i += stride) ps4[i] = make_uint4(kNone, kNone, kNone, kNone);
-    for (int64_t i = (tot / 4) * 4 + tid; i < tot; i += stride) G.PS[i] = kNone;
+    uint4* e4 = (uint4*)G.E;
+    for (int64_t i = tid; i < tot / 2; i += stride) e4[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (int64_t i = (tot / 2) * 2 + tid; i < tot; i += stride) G.E[i] = ~0ull;
     for (int64_t i = tid; i < 8 + 4 * kSpread * kSpreadStride; i += stride) G.ctl[i] = 0ull;
 }
 
@@ -132,8 +134,7 @@ __global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* s
         }
         G.F[0][s] |= 1ull << j;
         G.VM[s] |= 1ull << j;
-        G.PS[(size_t)s * G.k + j] = s;
-        G.DS[(size_t)s * G.k + j] = 0;
+        G.E[(size_t)s * G.k + j] = s;  // round 0, parent itself
     }
     for (int j = 0; j < 64; ++j) G.start[j] = 0;
     G.ctl[0] = ((unsigned long long)cnt << 32) | edges;  // qcnt slot 0
@@ -186,8 +187,7 @@ __global__ void ms_join_kernel(MsGroupDev* groups, int32_t gi, uint32_t r, const
         }
         F[s] |= 1ull << j;
         G.VM[s] |= 1ull << j;
-        G.PS[(size_t)s * G.k + j] = s;
-        G.DS[(size_t)s * G.k + j] = r;
+        G.E[(size_t)s * G.k + j] = ((unsigned long long)r << 32) | s;
         G.start[j] = r;
         bits |= 1ull << j;
     }
@@ -235,8 +235,9 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
         for (int i = 0; i < kRows; ++i) {
             const int vi = (t >> 6) + i * (kBlock / 64);
             const bool ok = vi < nv && j < ku && ((tv[vi < nv ? vi : 0] >> j) & 1ull);
-            lp[i] = ok ? G.PS[(size_t)(v0 + vi) * k + j] : 0u;
-            ld[i] = ok ? G.DS[(size_t)(v0 + vi) * k + j] : 0u;
+            const unsigned long long e = ok ? G.E[(size_t)(v0 + vi) * k + j] : 0ull;
+            lp[i] = (uint32_t)e;
+            ld[i] = (uint32_t)(e >> 32);
         }
 #pragma unroll
         for (int i = 0; i < kRows; ++i) {
@@ -277,6 +278,7 @@ struct MsPushPolicy {
     const unsigned long long* Fc;
     unsigned long long* Fn;
     const QueueOut* out;
+    uint32_t arrive;  // round in which the pairs found now enter the frontier
     uint32_t found;
     uint32_t dsum;
     static constexpr bool kSkipDead = false;
@@ -291,14 +293,17 @@ struct MsPushPolicy {
             const unsigned long long seen = G->VM[v] | Fc[v];
             const unsigned long long cand = Fc[u] & G->kmask & ~seen;
             if (cand) {
+                const unsigned long long key = ((unsigned long long)arrive << 32) | u;
                 const unsigned long long old = atomicOr(&Fn[v], cand);
                 claim = old == 0ull;
+                // every pair found this round arrives in round r + 1: the
+                // minimum entry holds the smallest parent
                 unsigned long long bits = cand;
                 while (bits) {
                     const int j = __ffsll((long long)bits) - 1;
                     bits &= bits - 1;
-                    uint32_t* pp = G->PS + (size_t)v * G->k + j;
-                    if (u < *pp) atomicMin(pp, u);
+                    unsigned long long* pp = G->E + (size_t)v * G->k + j;
+                    if (key < *pp) atomicMin(pp, key);
                 }
                 if (claim) dv = G->deg[v];
             }
@@ -331,18 +336,42 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
     return x;
 }
 
-// Records the distance of the bits that entered the frontier (fold of F_r
-// into VM), one row per bit.
-__device__ __forceinline__ void ms_fold(const MsGroupDev& G, uint32_t r, uint32_t v,
-                                        unsigned long long vm, unsigned long long f) {
-    G.VM[v] = vm | f;
-    uint32_t* ds = G.DS + (size_t)v * G.k;
-    while (f) {
-        const int j = __ffsll((long long)f) - 1;
-        f &= f - 1;
-        ds[j] = r;
+// row_l[j] = val_l for every lane l and every set bit j of bits_l
+// (wave-uniform call).  The stores are dealt out over the lanes in slot
+// order, lane l's bits taking consecutive slots, so one store instruction
+// writes up to 64 entries and the entries of one row sit in neighbouring
+// lanes: a row costs a few cache-line writes instead of one write request
+// per bit (a loop over each lane's own bits issues one store per bit with
+// every lane on a different row).
+__device__ __forceinline__ void wave_store_bits(unsigned long long bits, unsigned long long* row,
+                                                unsigned long long val) {
+    const int l = lane_id();
+    const uint32_t c = (uint32_t)__popcll(bits);
+    const uint32_t inc = wave_incl_sum(c);
+    const uint32_t total = __shfl(inc, 63, 64);
+    const uint32_t ex = inc - c;
+    for (uint32_t s0 = 0; s0 < total; s0 += 64u) {
+        const uint32_t s = s0 + (uint32_t)l;
+        // slot s belongs to the last lane whose first slot is <= s; that
+        // lane has at least s - ex + 1 bits, since the next lane starts
+        // after s
+        int o = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1)
+            if (__shfl(ex, o + st, 64) <= s) o += st;
+        const unsigned long long b = shfl64(bits, o);
+        const uint64_t rp = shfl64((uint64_t)(uintptr_t)row, o);
+        const unsigned long long v = shfl64(val, o);
+        const uint32_t k = s - __shfl(ex, o, 64);
+        if (s < total) {
+            const uint32_t lo = (uint32_t)__popc((uint32_t)b);
+            const uint32_t j = k < lo ? select_bit((uint32_t)b, k)
+                                      : 32u + select_bit((uint32_t)(b >> 32), k - lo);
+            ((unsigned long long*)(uintptr_t)rp)[j] = v;
+        }
     }
 }
+
 
 // Dense scan of one plan item that is a run of <= 64 vertices: the run's
 // edges are contiguous, so the wavefront walks them 64 at a time (coalesced
@@ -371,7 +400,7 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
     }
     const uint32_t s = in ? (uint32_t)(o0 - base) : 0xFFFFFFFFu;
     const uint32_t d = (uint32_t)(o1 - o0);
-    if (in && f) ms_fold(G, r, v, vm, f);
+    if (in && f) G.VM[v] = vm | f;  // fold of F_r
     const unsigned long long need = (in && d) ? (G.kmask & ~(vm | f)) : 0ull;
     unsigned long long acc = 0ull;
     uint64_t live = ballot(need != 0ull);
@@ -424,13 +453,8 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
             }
             unsigned long long excl = shfl_up64(incl, 1);
             if (l - 1 < seg) excl = 0ull;
-            unsigned long long first = add & ~excl;
-            uint32_t* ps = G.PS + (size_t)(vb + (uint32_t)o) * G.k;
-            while (first) {
-                const int j = __ffsll((long long)first) - 1;
-                first &= first - 1;
-                ps[j] = u[k];
-            }
+            wave_store_bits(add & ~excl, G.E + (size_t)(vb + (uint32_t)o) * G.k,
+                            ((unsigned long long)(r + 1u) << 32) | u[k]);
             // each vertex takes the OR of its lanes in this window
             uint32_t last = 0;
             bool hasw = false;
@@ -470,7 +494,7 @@ __device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, u
     const uint32_t v = it.x;
     const int64_t ob = G.off[v], oe = G.off[v + 1];
     const unsigned long long f = Fc[v], vm = G.VM[v];
-    if ((int64_t)it.z == ob && f && l == 0) ms_fold(G, r, v, vm, f);
+    if ((int64_t)it.z == ob && f && l == 0) G.VM[v] = vm | f;  // the first piece folds v
     const unsigned long long need = G.kmask & ~(vm | f);
     unsigned long long acc = 0ull;
     for (uint32_t e = it.z; e < it.w && need && acc != need; e += 128u) {
@@ -484,11 +508,14 @@ __device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, u
             const uint32_t u = k ? u1 : u0;
             const unsigned long long add = (k ? f1 : f0) & need & ~acc;
             unsigned long long first = add & ~wave_excl_or64(add);
+            // pieces of one list may run concurrently: atomic minimum of the
+            // pair entry (every candidate this round has the same arrival)
+            const unsigned long long key = ((unsigned long long)(r + 1u) << 32) | u;
             while (first) {
                 const int j = __ffsll((long long)first) - 1;
                 first &= first - 1;
-                uint32_t* pp = G.PS + (size_t)v * G.k + j;
-                if (u < *pp) atomicMin(pp, u);
+                unsigned long long* pp = G.E + (size_t)v * G.k + j;
+                if (key < *pp) atomicMin(pp, key);
             }
             acc |= wave_or64(add);
         }
@@ -602,14 +629,14 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
              v += (int64_t)gridDim.x * blockDim.x)
             Fclr[v] = 0ull;
         if (s_push[gi]) {
-            // fold the frontier list into VM and record distances
+            // fold the frontier list into VM
             const uint32_t cnt = (uint32_t)(t >> 32);
             const uint32_t* Qc = G.Q[r & 1];
             const unsigned long long* Fc = G.F[r % 3];
             for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
                  i += gridDim.x * blockDim.x) {
                 const uint32_t u = Qc[i];
-                ms_fold(G, r, u, G.VM[u], Fc[u]);
+                G.VM[u] |= Fc[u];
             }
         }
     }
@@ -634,7 +661,7 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
         uint32_t f0 = 0, d0 = 0;
         if (s_push[gi]) {
             if (edges) {
-                MsPushPolicy pol{&G, Fc, Fn, &out, 0u, 0u};
+                MsPushPolicy pol{&G, Fc, Fn, &out, r + 1u, 0u, 0u};
                 const uint32_t wc = s_wc[gi];
                 const uint32_t eb = local * wc;
                 expand_range(G.Q[r & 1], G.P[r & 1], cnt, edges, G.off, eb, min(edges, eb + wc),
@@ -704,7 +731,7 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t ms_group_bytes(int64_t n, int64_t k) {
     return 4 * al256((size_t)n * 8) + 4 * al256((size_t)(n + 64) * 4) +
            al256((8 + 4 * kSpread * kSpreadStride) * 8) + 2 * al256(64 * 8) + al256(64 * 4) +
-           2 * al256((size_t)n * (size_t)k * 4);
+           al256((size_t)n * (size_t)k * 8);
 }
 
 // Packs queries on the same graph 64 to a group (in submission order).
@@ -836,8 +863,7 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         G.start = (uint32_t*)p; p += al256(64 * 4);
         G.k = (uint32_t)std::max<size_t>(gq.size(), joinable ? kcap : 0u);
         G.kused = (uint32_t)gq.size();
-        G.PS = (uint32_t*)p; p += al256((size_t)n * G.k * 4);
-        G.DS = (uint32_t*)p; p += al256((size_t)n * G.k * 4);
+        G.E = (unsigned long long*)p; p += al256((size_t)n * G.k * 8);
         for (size_t j = 0; j < gq.size(); ++j) {
             hsrc[(size_t)i * 64 + j] = (uint32_t)qs[gq[j]].src;
             rowsD[(size_t)i * 64 + j] = qs[gq[j]].dist;
