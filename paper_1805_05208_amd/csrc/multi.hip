@@ -373,6 +373,78 @@ __device__ __forceinline__ void wave_store_bits(unsigned long long bits, unsigne
 }
 
 
+constexpr uint32_t kMsEmit = 256;  // next-list entries a wavefront buffers
+
+struct MsEmitBuf {
+    uint32_t v[kMsEmit];
+    uint32_t d[kMsEmit];
+};
+
+// A wavefront's buffer of next-list entries for one group: the dense scan
+// appends the vertices it finds in LDS and reserves their room in the
+// group's list with one atomic per flush.  The list's counter is a single
+// address for the whole grid, so one reservation per plan item serialised
+// (a round whose frontier shrinks to ~10^5 scattered vertices spent about a
+// millisecond on them).
+struct MsEmitter {
+    MsEmitBuf* b;
+    uint32_t n;  // buffered entries (wave-uniform)
+};
+
+// Writes the buffered entries (ids, degree prefix) to `out` after one
+// reservation; nothing is written once the list has been abandoned.
+// Wave-uniform.
+__device__ __forceinline__ void ms_emit_flush(MsEmitter& e, const QueueOut& out) {
+    if (e.n == 0u) return;
+    wave_lds_sync();
+    const int l = lane_id();
+    const uint32_t n = e.n;
+    uint32_t ds = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += 64u) {
+        const uint32_t i = i0 + (uint32_t)l;
+        ds += wave_sum(i < n ? e.b->d[i] : 0u);
+    }
+    unsigned long long packed = ~0ull;
+    if (l == 0 && *(volatile unsigned long long*)out.qover == 0) {
+        packed = atomicAdd(out.qcnt, ((unsigned long long)n << 32) | ds);
+        if ((uint64_t)(packed >> 32) + n + (uint32_t)packed + ds > out.qlimit) {
+            *out.qover = 1ull;
+            packed = ~0ull;
+        }
+    }
+    packed = shfl64(packed, 0);
+    if (packed != ~0ull) {
+        const uint32_t pos = (uint32_t)(packed >> 32);
+        uint32_t dp = (uint32_t)packed;
+        for (uint32_t i0 = 0; i0 < n; i0 += 64u) {
+            const uint32_t i = i0 + (uint32_t)l;
+            const uint32_t x = i < n ? e.b->d[i] : 0u;
+            const uint32_t inc = wave_incl_sum(x);
+            if (i < n) {
+                out.Q[pos + i] = e.b->v[i];
+                out.P[pos + i] = dp + inc - x;
+            }
+            dp += __shfl(inc, 63, 64);
+        }
+    }
+    wave_lds_sync();  // every lane has read the buffer before it refills
+    e.n = 0u;
+}
+
+// Appends the lanes of m (those with take set) with their degrees; `out` is
+// the list the buffer holds entries for.
+__device__ __forceinline__ void ms_emit_add(MsEmitter& e, const QueueOut& out, bool take,
+                                            uint32_t v, uint32_t dv, uint64_t m) {
+    const uint32_t k = (uint32_t)__popcll(m);
+    if (e.n + k > kMsEmit) ms_emit_flush(e, out);
+    if (take) {
+        const uint32_t p = e.n + mbcnt(m);
+        e.b->v[p] = v;
+        e.b->d[p] = dv;
+    }
+    e.n += k;
+}
+
 // Dense scan of one plan item that is a run of <= 64 vertices: the run's
 // edges are contiguous, so the wavefront walks them 64 at a time (coalesced
 // neighbour loads) and finds, for every vertex and every unseen bit, the
@@ -382,8 +454,9 @@ __device__ __forceinline__ void wave_store_bits(unsigned long long bits, unsigne
 // stops being scanned once all its unseen bits are found.
 __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uint4 it,
                                             const unsigned long long* __restrict__ Fc,
-                                            unsigned long long* Fn, const QueueOut& out,
-                                            bool emit, uint32_t& found, uint32_t& dsum) {
+                                            unsigned long long* Fn, MsEmitter& em,
+                                            const QueueOut& out, bool emit, uint32_t& found,
+                                            uint32_t& dsum) {
     const int l = lane_id();
     const uint32_t vb = it.x, nv = it.y - it.x;
     const bool in = (uint32_t)l < nv;
@@ -479,7 +552,7 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
         dsum += d;
     }
     const uint64_t m = ballot(got);
-    if (m && emit) wave_direct_emit(got, v, d, m, out);
+    if (m && emit) ms_emit_add(em, out, got, v, d, m);
 }
 
 // Dense scan of a piece of one long list: first contributors within the
@@ -488,8 +561,9 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
 // that sets the first bit counts the vertex.
 __device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, uint4 it,
                                               const unsigned long long* __restrict__ Fc,
-                                              unsigned long long* Fn, const QueueOut& out,
-                                              bool emit, uint32_t& found, uint32_t& dsum) {
+                                              unsigned long long* Fn, MsEmitter& em,
+                                              const QueueOut& out, bool emit, uint32_t& found,
+                                              uint32_t& dsum) {
     const int l = lane_id();
     const uint32_t v = it.x;
     const int64_t ob = G.off[v], oe = G.off[v + 1];
@@ -528,7 +602,7 @@ __device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, u
         dsum += (uint32_t)(oe - ob);
     }
     const uint64_t m = ballot(claim && l == 0);
-    if (m && emit) wave_direct_emit(claim && l == 0, v, (uint32_t)(oe - ob), m, out);
+    if (m && emit) ms_emit_add(em, out, claim && l == 0, v, (uint32_t)(oe - ob), m);
 }
 
 // One workgroup per CU at most (up to 128 VGPRs): the dense scan's state
@@ -544,7 +618,21 @@ struct MsShared {
     uint32_t emit[kMaxGroups];
     uint32_t found[kMaxGroups];
     uint32_t fdsum[kMaxGroups];
+    MsEmitBuf eb[kRWaves];  // one next-list buffer per wavefront
 };
+
+// Group G's list for round r + 1 (a frontier above the dense threshold
+// abandons it, except under forced push).
+__device__ __forceinline__ QueueOut ms_next_list(const MsGroupDev& G, uint32_t r, int32_t force_dir) {
+    QueueOut out;
+    out.Q = G.Q[(r + 1) & 1];
+    out.P = G.P[(r + 1) & 1];
+    out.qcnt = &G.ctl[(r + 1) & 3u];
+    out.qover = &G.ctl[4 + ((r + 1) & 3u)];
+    out.qlimit = force_dir == 1 ? ~0ull : G.dense_thresh;
+    out.tot = nullptr;
+    return out;
+}
 
 // One round r for every group (workgroup-uniform); returns false when no
 // group has a frontier in round r (every group has finished).
@@ -643,18 +731,17 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
     const uint32_t total = s_units[NG];
     int gi = 0;
     uint32_t found = 0, dsum = 0;
+    // this wavefront's buffered next-list entries belong to group egi
+    MsEmitter em;
+    em.b = &sh.eb[wib];
+    em.n = 0u;
+    int egi = -1;
     for (uint32_t unit = gwave; unit < total; unit += nwaves) {
         while (unit >= s_units[gi + 1]) ++gi;
         const MsGroupDev& G = A.groups[gi];
         const unsigned long long t = s_tot[gi];
         const uint32_t cnt = (uint32_t)(t >> 32), edges = (uint32_t)t;
-        QueueOut out;
-        out.Q = G.Q[(r + 1) & 1];
-        out.P = G.P[(r + 1) & 1];
-        out.qcnt = &G.ctl[(r + 1) & 3u];
-        out.qover = &G.ctl[4 + ((r + 1) & 3u)];
-        out.qlimit = A.force_dir == 1 ? ~0ull : G.dense_thresh;
-        out.tot = nullptr;
+        const QueueOut out = ms_next_list(G, r, A.force_dir);
         const unsigned long long* Fc = G.F[r % 3];
         unsigned long long* Fn = G.F[(r + 1) % 3];
         const uint32_t local = unit - s_units[gi];
@@ -670,11 +757,15 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
                 d0 = pol.dsum;
             }
         } else {
+            if (s_emit[gi] && egi != gi) {
+                if (egi >= 0) ms_emit_flush(em, ms_next_list(A.groups[egi], r, A.force_dir));
+                egi = gi;
+            }
             const uint4 it = G.plan[local];
             if (it.z == kPlanHub)
-                ms_pull_run(G, r, it, Fc, Fn, out, s_emit[gi] != 0, f0, d0);
+                ms_pull_run(G, r, it, Fc, Fn, em, out, s_emit[gi] != 0, f0, d0);
             else
-                ms_pull_piece(G, r, it, Fc, Fn, out, s_emit[gi] != 0, f0, d0);
+                ms_pull_piece(G, r, it, Fc, Fn, em, out, s_emit[gi] != 0, f0, d0);
         }
         f0 = wave_sum(f0);
         d0 = wave_sum(d0);
@@ -683,6 +774,7 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
             atomicAdd(&s_fdsum[gi], d0);
         }
     }
+    if (egi >= 0) ms_emit_flush(em, ms_next_list(A.groups[egi], r, A.force_dir));
     __syncthreads();
     if (threadIdx.x < (unsigned)NG && s_found[threadIdx.x]) {
         const MsGroupDev& G = A.groups[threadIdx.x];
