@@ -273,106 +273,6 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
     }
 }
 
-struct MsPushPolicy {
-    const MsGroupDev* G;
-    const unsigned long long* Fc;
-    unsigned long long* Fn;
-    const QueueOut* out;
-    uint32_t arrive;  // round in which the pairs found now enter the frontier
-    uint32_t found;
-    uint32_t dsum;
-    static constexpr bool kSkipDead = false;
-
-    __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
-
-    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e, bool) {
-        bool claim = false;
-        uint32_t v = 0, dv = 0;
-        if (act) {
-            v = (uint32_t)G->nbr[e];
-            const unsigned long long seen = G->VM[v] | Fc[v];
-            const unsigned long long cand = Fc[u] & G->kmask & ~seen;
-            if (cand) {
-                const unsigned long long key = ((unsigned long long)arrive << 32) | u;
-                const unsigned long long old = atomicOr(&Fn[v], cand);
-                claim = old == 0ull;
-                // every pair found this round arrives in round r + 1: the
-                // minimum entry holds the smallest parent
-                unsigned long long bits = cand;
-                while (bits) {
-                    const int j = __ffsll((long long)bits) - 1;
-                    bits &= bits - 1;
-                    unsigned long long* pp = G->E + (size_t)v * G->k + j;
-                    if (key < *pp) atomicMin(pp, key);
-                }
-                if (claim) dv = G->deg[v];
-            }
-        }
-        const uint64_t m = ballot(claim);
-        if (m) {
-            wave_direct_emit(claim, v, dv, m, *out);
-            if (claim) {
-                found += 1;
-                dsum += dv;
-            }
-        }
-    }
-    __device__ __forceinline__ void window_done() {}
-};
-
-__device__ __forceinline__ unsigned long long shfl_up64(unsigned long long x, int d) {
-    const uint32_t lo = __shfl_up((uint32_t)x, d, 64);
-    const uint32_t hi = __shfl_up((uint32_t)(x >> 32), d, 64);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)x, d, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), d, 64);
-        x |= ((unsigned long long)hi << 32) | lo;
-    }
-    return x;
-}
-
-// row_l[j] = val_l for every lane l and every set bit j of bits_l
-// (wave-uniform call).  The stores are dealt out over the lanes in slot
-// order, lane l's bits taking consecutive slots, so one store instruction
-// writes up to 64 entries and the entries of one row sit in neighbouring
-// lanes: a row costs a few cache-line writes instead of one write request
-// per bit (a loop over each lane's own bits issues one store per bit with
-// every lane on a different row).
-__device__ __forceinline__ void wave_store_bits(unsigned long long bits, unsigned long long* row,
-                                                unsigned long long val) {
-    const int l = lane_id();
-    const uint32_t c = (uint32_t)__popcll(bits);
-    const uint32_t inc = wave_incl_sum(c);
-    const uint32_t total = __shfl(inc, 63, 64);
-    const uint32_t ex = inc - c;
-    for (uint32_t s0 = 0; s0 < total; s0 += 64u) {
-        const uint32_t s = s0 + (uint32_t)l;
-        // slot s belongs to the last lane whose first slot is <= s; that
-        // lane has at least s - ex + 1 bits, since the next lane starts
-        // after s
-        int o = 0;
-#pragma unroll
-        for (int st = 32; st >= 1; st >>= 1)
-            if (__shfl(ex, o + st, 64) <= s) o += st;
-        const unsigned long long b = shfl64(bits, o);
-        const uint64_t rp = shfl64((uint64_t)(uintptr_t)row, o);
-        const unsigned long long v = shfl64(val, o);
-        const uint32_t k = s - __shfl(ex, o, 64);
-        if (s < total) {
-            const uint32_t lo = (uint32_t)__popc((uint32_t)b);
-            const uint32_t j = k < lo ? select_bit((uint32_t)b, k)
-                                      : 32u + select_bit((uint32_t)(b >> 32), k - lo);
-            ((unsigned long long*)(uintptr_t)rp)[j] = v;
-        }
-    }
-}
-
-
 constexpr uint32_t kMsEmit = 256;  // next-list entries a wavefront buffers
 
 struct MsEmitBuf {
@@ -444,6 +344,107 @@ __device__ __forceinline__ void ms_emit_add(MsEmitter& e, const QueueOut& out, b
     }
     e.n += k;
 }
+
+struct MsPushPolicy {
+    const MsGroupDev* G;
+    const unsigned long long* Fc;
+    unsigned long long* Fn;
+    const QueueOut* out;
+    MsEmitter* em;
+    uint32_t arrive;  // round in which the pairs found now enter the frontier
+    uint32_t found;
+    uint32_t dsum;
+    static constexpr bool kSkipDead = false;
+
+    __device__ __forceinline__ uint32_t aux(uint32_t) const { return 1u; }
+
+    __device__ __forceinline__ void edge(bool act, uint32_t u, uint32_t, int64_t e, bool) {
+        bool claim = false;
+        uint32_t v = 0, dv = 0;
+        if (act) {
+            v = (uint32_t)G->nbr[e];
+            const unsigned long long seen = G->VM[v] | Fc[v];
+            const unsigned long long cand = Fc[u] & G->kmask & ~seen;
+            if (cand) {
+                const unsigned long long key = ((unsigned long long)arrive << 32) | u;
+                const unsigned long long old = atomicOr(&Fn[v], cand);
+                claim = old == 0ull;
+                // every pair found this round arrives in round r + 1: the
+                // minimum entry holds the smallest parent
+                unsigned long long bits = cand;
+                while (bits) {
+                    const int j = __ffsll((long long)bits) - 1;
+                    bits &= bits - 1;
+                    unsigned long long* pp = G->E + (size_t)v * G->k + j;
+                    if (key < *pp) atomicMin(pp, key);
+                }
+                if (claim) dv = G->deg[v];
+            }
+        }
+        const uint64_t m = ballot(claim);
+        if (m) {
+            ms_emit_add(*em, *out, claim, v, dv, m);
+            if (claim) {
+                found += 1;
+                dsum += dv;
+            }
+        }
+    }
+    __device__ __forceinline__ void window_done() {}
+};
+
+__device__ __forceinline__ unsigned long long shfl_up64(unsigned long long x, int d) {
+    const uint32_t lo = __shfl_up((uint32_t)x, d, 64);
+    const uint32_t hi = __shfl_up((uint32_t)(x >> 32), d, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, d, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), d, 64);
+        x |= ((unsigned long long)hi << 32) | lo;
+    }
+    return x;
+}
+
+// row_l[j] = val_l for every lane l and every set bit j of bits_l
+// (wave-uniform call).  The stores are dealt out over the lanes in slot
+// order, lane l's bits taking consecutive slots, so one store instruction
+// writes up to 64 entries and the entries of one row sit in neighbouring
+// lanes: a row costs a few cache-line writes instead of one write request
+// per bit (a loop over each lane's own bits issues one store per bit with
+// every lane on a different row).
+__device__ __forceinline__ void wave_store_bits(unsigned long long bits, unsigned long long* row,
+                                                unsigned long long val) {
+    const int l = lane_id();
+    const uint32_t c = (uint32_t)__popcll(bits);
+    const uint32_t inc = wave_incl_sum(c);
+    const uint32_t total = __shfl(inc, 63, 64);
+    const uint32_t ex = inc - c;
+    for (uint32_t s0 = 0; s0 < total; s0 += 64u) {
+        const uint32_t s = s0 + (uint32_t)l;
+        // slot s belongs to the last lane whose first slot is <= s; that
+        // lane has at least s - ex + 1 bits, since the next lane starts
+        // after s
+        int o = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1)
+            if (__shfl(ex, o + st, 64) <= s) o += st;
+        const unsigned long long b = shfl64(bits, o);
+        const uint64_t rp = shfl64((uint64_t)(uintptr_t)row, o);
+        const unsigned long long v = shfl64(val, o);
+        const uint32_t k = s - __shfl(ex, o, 64);
+        if (s < total) {
+            const uint32_t lo = (uint32_t)__popc((uint32_t)b);
+            const uint32_t j = k < lo ? select_bit((uint32_t)b, k)
+                                      : 32u + select_bit((uint32_t)(b >> 32), k - lo);
+            ((unsigned long long*)(uintptr_t)rp)[j] = v;
+        }
+    }
+}
+
 
 // Dense scan of one plan item that is a run of <= 64 vertices: the run's
 // edges are contiguous, so the wavefront walks them 64 at a time (coalesced
@@ -746,9 +747,16 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
         unsigned long long* Fn = G.F[(r + 1) % 3];
         const uint32_t local = unit - s_units[gi];
         uint32_t f0 = 0, d0 = 0;
+        if (s_push[gi] || s_emit[gi]) {
+            // the buffered entries belong to one group's list
+            if (egi != gi) {
+                if (egi >= 0) ms_emit_flush(em, ms_next_list(A.groups[egi], r, A.force_dir));
+                egi = gi;
+            }
+        }
         if (s_push[gi]) {
             if (edges) {
-                MsPushPolicy pol{&G, Fc, Fn, &out, r + 1u, 0u, 0u};
+                MsPushPolicy pol{&G, Fc, Fn, &out, &em, r + 1u, 0u, 0u};
                 const uint32_t wc = s_wc[gi];
                 const uint32_t eb = local * wc;
                 expand_range(G.Q[r & 1], G.P[r & 1], cnt, edges, G.off, eb, min(edges, eb + wc),
@@ -757,10 +765,6 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
                 d0 = pol.dsum;
             }
         } else {
-            if (s_emit[gi] && egi != gi) {
-                if (egi >= 0) ms_emit_flush(em, ms_next_list(A.groups[egi], r, A.force_dir));
-                egi = gi;
-            }
             const uint4 it = G.plan[local];
             if (it.z == kPlanHub)
                 ms_pull_run(G, r, it, Fc, Fn, em, out, s_emit[gi] != 0, f0, d0);
