@@ -28,6 +28,9 @@
 namespace gb {
 
 constexpr int kMaxGroups = 64;
+// last round a group with 4-byte pair entries may run (its arrivals, at most
+// this round + 1, fill the 8-bit round field)
+constexpr uint32_t kNarrowRounds = 254;
 // 64-edge windows a wavefront of the dense scan loads before it updates
 constexpr int kMsWin = 2;
 
@@ -52,14 +55,23 @@ struct MsGroupDev {
     uint32_t nplan;
     uint32_t k;                 // capacity: sources the staging holds per vertex
     uint32_t kused;             // sources in the group so far (bits 0 .. kused-1)
-    // vertex-major pair entries E[v * k + j] = (round of arrival << 32) |
-    // parent, written when the pair is found; ~0 until then
-    unsigned long long* E;
+    // vertex-major pair entries E[v * k + j], written when the pair is found
+    // and ~0 until then: (round of arrival << 32) | parent in 8 bytes, or,
+    // when narrow, (round << 24) | parent in 4 bytes (graphs of at most 2^24
+    // vertices, groups that take no arrivals, rounds up to kNarrowRounds)
+    void* E;
+    uint32_t narrow;
     uint32_t* start;            // round at which source j joined the group (64)
 };
 
+__device__ __host__ __forceinline__ unsigned long long* ent64(const MsGroupDev& G) {
+    return (unsigned long long*)G.E;
+}
+__device__ __host__ __forceinline__ uint32_t* ent32(const MsGroupDev& G) { return (uint32_t*)G.E; }
+
 struct MsArgs {
     MsGroupDev* groups;
+    uint32_t* ovf;   // set when a narrow group reached round kNarrowRounds + 1
     int32_t ngroups;
     int32_t force_dir;
     int32_t light;
@@ -110,19 +122,21 @@ __global__ __launch_bounds__(kBlock) void ms_init_kernel(MsGroupDev* groups, int
     }
     // pair entries start at ~0 so that sparse rounds can take atomicMin (the
     // final transpose reads only reached pairs)
-    const int64_t tot = G.n * (int64_t)G.k;
+    const int64_t words = G.n * (int64_t)G.k * (G.narrow ? 1 : 2);  // 4-byte words
     uint4* e4 = (uint4*)G.E;
-    for (int64_t i = tid; i < tot / 2; i += stride) e4[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (int64_t i = (tot / 2) * 2 + tid; i < tot; i += stride) G.E[i] = ~0ull;
+    for (int64_t i = tid; i < words / 4; i += stride) e4[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (int64_t i = (words / 4) * 4 + tid; i < words; i += stride) ((uint32_t*)G.E)[i] = ~0u;
     for (int64_t i = tid; i < 8 + 4 * kSpread * kSpreadStride; i += stride) G.ctl[i] = 0ull;
 }
 
 // After init: frontier F_0 = source bits, list Q_0 = distinct sources; the
 // sources' own entries (distance 0, parent itself, visited) are set here so
 // that an isolated source needs no traversal work.
-__global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* srcs, int32_t k) {
+__global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* srcs, int32_t k,
+                               uint32_t* ovf) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const MsGroupDev G = groups[gi];
+    if (ovf) *ovf = 0u;
     uint32_t cnt = 0, edges = 0;
     for (int j = 0; j < k; ++j) {
         const uint32_t s = srcs[j];
@@ -134,7 +148,9 @@ __global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* s
         }
         G.F[0][s] |= 1ull << j;
         G.VM[s] |= 1ull << j;
-        G.E[(size_t)s * G.k + j] = s;  // round 0, parent itself
+        // round 0, parent itself
+        if (G.narrow) ent32(G)[(size_t)s * G.k + j] = s;
+        else ent64(G)[(size_t)s * G.k + j] = s;
     }
     for (int j = 0; j < 64; ++j) G.start[j] = 0;
     G.ctl[0] = ((unsigned long long)cnt << 32) | edges;  // qcnt slot 0
@@ -187,7 +203,7 @@ __global__ void ms_join_kernel(MsGroupDev* groups, int32_t gi, uint32_t r, const
         }
         F[s] |= 1ull << j;
         G.VM[s] |= 1ull << j;
-        G.E[(size_t)s * G.k + j] = ((unsigned long long)r << 32) | s;
+        ent64(G)[(size_t)s * G.k + j] = ((unsigned long long)r << 32) | s;  // never narrow
         G.start[j] = r;
         bits |= 1ull << j;
     }
@@ -195,6 +211,38 @@ __global__ void ms_join_kernel(MsGroupDev* groups, int32_t gi, uint32_t r, const
     if (qvalid) G.ctl[r & 3u] += add;
     G.kmask |= bits;
     G.kused = j0 + cnt;
+}
+
+// vertex rows of a transpose tile each thread loads
+constexpr int kTileRows = 64 / (kBlock / 64);
+
+// Thread t's share of a 64-vertex tile of pair entries (column t % 64, rows
+// t / 64 + 16 i): parent and round of arrival of each reached pair.  Every
+// load is issued before any is used, so a thread keeps kTileRows reads in
+// flight; pairs the search never reached are not read (their row entries
+// are written as unreachable).
+template <class T>
+__device__ __forceinline__ void ms_load_tile(const T* E, int64_t v0, int nv, int k, int ku, int t,
+                                             const unsigned long long* tv, uint32_t* lp,
+                                             uint32_t* ld) {
+    const int j = t & 63;
+    T e[kTileRows];
+#pragma unroll
+    for (int i = 0; i < kTileRows; ++i) {
+        const int vi = (t >> 6) + i * (kBlock / 64);
+        const bool ok = vi < nv && j < ku && ((tv[vi < nv ? vi : 0] >> j) & 1ull);
+        e[i] = ok ? E[(size_t)(v0 + vi) * k + j] : (T)0;
+    }
+#pragma unroll
+    for (int i = 0; i < kTileRows; ++i) {
+        if constexpr (sizeof(T) == 4) {
+            lp[i] = (uint32_t)e[i] & 0xFFFFFFu;
+            ld[i] = (uint32_t)e[i] >> 24;
+        } else {
+            lp[i] = (uint32_t)e[i];
+            ld[i] = (uint32_t)(e[i] >> 32);
+        }
+    }
 }
 
 // Final layout: row j of the caller's output = source j.  Each workgroup
@@ -226,21 +274,13 @@ __global__ __launch_bounds__(kBlock) void ms_transpose_kernel(MsGroupDev* groups
         if (t < nv) tv[t] = G.VM[v0 + t];
         __syncthreads();
         const int j = t & 63;
-        // all of this thread's loads are issued before any LDS store, so each
-        // thread keeps 32 reads in flight; pairs the search never reached are
-        // not read (their row entries are written as unreachable below)
-        constexpr int kRows = 64 / (kBlock / 64);
-        uint32_t lp[kRows], ld[kRows];
+        uint32_t lp[kTileRows], ld[kTileRows];
+        if (G.narrow)
+            ms_load_tile(ent32(G), v0, nv, k, ku, t, tv, lp, ld);
+        else
+            ms_load_tile(ent64(G), v0, nv, k, ku, t, tv, lp, ld);
 #pragma unroll
-        for (int i = 0; i < kRows; ++i) {
-            const int vi = (t >> 6) + i * (kBlock / 64);
-            const bool ok = vi < nv && j < ku && ((tv[vi < nv ? vi : 0] >> j) & 1ull);
-            const unsigned long long e = ok ? G.E[(size_t)(v0 + vi) * k + j] : 0ull;
-            lp[i] = (uint32_t)e;
-            ld[i] = (uint32_t)(e >> 32);
-        }
-#pragma unroll
-        for (int i = 0; i < kRows; ++i) {
+        for (int i = 0; i < kTileRows; ++i) {
             const int vi = (t >> 6) + i * (kBlock / 64);
             tp[vi][j] = lp[i];
             td[vi][j] = ld[i];
@@ -366,7 +406,6 @@ struct MsPushPolicy {
             const unsigned long long seen = G->VM[v] | Fc[v];
             const unsigned long long cand = Fc[u] & G->kmask & ~seen;
             if (cand) {
-                const unsigned long long key = ((unsigned long long)arrive << 32) | u;
                 const unsigned long long old = atomicOr(&Fn[v], cand);
                 claim = old == 0ull;
                 // every pair found this round arrives in round r + 1: the
@@ -375,8 +414,16 @@ struct MsPushPolicy {
                 while (bits) {
                     const int j = __ffsll((long long)bits) - 1;
                     bits &= bits - 1;
-                    unsigned long long* pp = G->E + (size_t)v * G->k + j;
-                    if (key < *pp) atomicMin(pp, key);
+                    const size_t at = (size_t)v * G->k + j;
+                    if (G->narrow) {
+                        const uint32_t key = (arrive << 24) | u;
+                        uint32_t* pp = ent32(*G) + at;
+                        if (key < *pp) atomicMin(pp, key);
+                    } else {
+                        const unsigned long long key = ((unsigned long long)arrive << 32) | u;
+                        unsigned long long* pp = ent64(*G) + at;
+                        if (key < *pp) atomicMin(pp, key);
+                    }
                 }
                 if (claim) dv = G->deg[v];
             }
@@ -416,8 +463,8 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
 // lanes: a row costs a few cache-line writes instead of one write request
 // per bit (a loop over each lane's own bits issues one store per bit with
 // every lane on a different row).
-__device__ __forceinline__ void wave_store_bits(unsigned long long bits, unsigned long long* row,
-                                                unsigned long long val) {
+template <class T>
+__device__ __forceinline__ void wave_store_bits(unsigned long long bits, T* row, T val) {
     const int l = lane_id();
     const uint32_t c = (uint32_t)__popcll(bits);
     const uint32_t inc = wave_incl_sum(c);
@@ -434,13 +481,15 @@ __device__ __forceinline__ void wave_store_bits(unsigned long long bits, unsigne
             if (__shfl(ex, o + st, 64) <= s) o += st;
         const unsigned long long b = shfl64(bits, o);
         const uint64_t rp = shfl64((uint64_t)(uintptr_t)row, o);
-        const unsigned long long v = shfl64(val, o);
+        T v;
+        if constexpr (sizeof(T) == 8) v = (T)shfl64((uint64_t)val, o);
+        else v = (T)__shfl((uint32_t)val, o, 64);
         const uint32_t k = s - __shfl(ex, o, 64);
         if (s < total) {
             const uint32_t lo = (uint32_t)__popc((uint32_t)b);
             const uint32_t j = k < lo ? select_bit((uint32_t)b, k)
                                       : 32u + select_bit((uint32_t)(b >> 32), k - lo);
-            ((unsigned long long*)(uintptr_t)rp)[j] = v;
+            ((T*)(uintptr_t)rp)[j] = v;
         }
     }
 }
@@ -527,8 +576,12 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
             }
             unsigned long long excl = shfl_up64(incl, 1);
             if (l - 1 < seg) excl = 0ull;
-            wave_store_bits(add & ~excl, G.E + (size_t)(vb + (uint32_t)o) * G.k,
-                            ((unsigned long long)(r + 1u) << 32) | u[k]);
+            const size_t row = (size_t)(vb + (uint32_t)o) * G.k;
+            if (G.narrow)
+                wave_store_bits(add & ~excl, ent32(G) + row, ((r + 1u) << 24) | u[k]);
+            else
+                wave_store_bits(add & ~excl, ent64(G) + row,
+                                ((unsigned long long)(r + 1u) << 32) | u[k]);
             // each vertex takes the OR of its lanes in this window
             uint32_t last = 0;
             bool hasw = false;
@@ -585,12 +638,19 @@ __device__ __forceinline__ void ms_pull_piece(const MsGroupDev& G, uint32_t r, u
             unsigned long long first = add & ~wave_excl_or64(add);
             // pieces of one list may run concurrently: atomic minimum of the
             // pair entry (every candidate this round has the same arrival)
-            const unsigned long long key = ((unsigned long long)(r + 1u) << 32) | u;
             while (first) {
                 const int j = __ffsll((long long)first) - 1;
                 first &= first - 1;
-                unsigned long long* pp = G.E + (size_t)v * G.k + j;
-                if (key < *pp) atomicMin(pp, key);
+                const size_t at = (size_t)v * G.k + j;
+                if (G.narrow) {
+                    const uint32_t key = ((r + 1u) << 24) | u;
+                    uint32_t* pp = ent32(G) + at;
+                    if (key < *pp) atomicMin(pp, key);
+                } else {
+                    const unsigned long long key = ((unsigned long long)(r + 1u) << 32) | u;
+                    unsigned long long* pp = ent64(G) + at;
+                    if (key < *pp) atomicMin(pp, key);
+                }
             }
             acc |= wave_or64(add);
         }
@@ -671,7 +731,14 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
         uint32_t acc = 0;
         for (int gi = 0; gi < NG; ++gi) {
             const MsGroupDev& G = A.groups[gi];
-            const unsigned long long t = s_tot[gi];
+            unsigned long long t = s_tot[gi];
+            if (G.narrow && r > kNarrowRounds && (t >> 32) != 0ull) {
+                // the 8-bit round field is full: the group stops here and
+                // the host runs the call again with 8-byte entries
+                t = 0ull;
+                s_tot[gi] = 0ull;
+                if (blockIdx.x == 0) *A.ovf = 1u;
+            }
             const uint32_t cnt = (uint32_t)(t >> 32), edges = (uint32_t)t;
             const bool qvalid = G.ctl[4 + (r & 3u)] == 0ull;
             bool push;
@@ -854,7 +921,7 @@ static std::vector<std::vector<int>> ms_plan(const std::vector<MsQuery>& qs) {
 
 static size_t ms_header_bytes(int NG) {
     return al256(sizeof(MsGroupDev) * NG) + al256((size_t)NG * 64 * 4) +
-           al256(4096 * kMaxGroups * 4) + al256((size_t)kBarWords * 4);
+           al256(4096 * kMaxGroups * 4) + al256((size_t)kBarWords * 4) + al256(4);
 }
 
 // Device bytes needed to run `groups` (at most kMaxGroups) together.
@@ -930,6 +997,7 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     uint32_t* dsrcs = (uint32_t*)p; p += al256((size_t)NG * 64 * 4);
     uint32_t* dlog = (uint32_t*)p; p += al256(4096 * kMaxGroups * 4);
     uint32_t* dbar = (uint32_t*)p; p += al256((size_t)kBarWords * 4);
+    uint32_t* dovf = (uint32_t*)p; p += al256(4);
     std::vector<MsGroupDev> hg(NG);
     std::vector<uint32_t> hsrc((size_t)NG * 64, 0);
     std::vector<int32_t*> rowsD((size_t)NG * 64, nullptr), rowsP((size_t)NG * 64, nullptr);
@@ -959,7 +1027,11 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         G.start = (uint32_t*)p; p += al256(64 * 4);
         G.k = (uint32_t)std::max<size_t>(gq.size(), joinable ? kcap : 0u);
         G.kused = (uint32_t)gq.size();
-        G.E = (unsigned long long*)p; p += al256((size_t)n * G.k * 8);
+        // 4-byte entries where a parent fits in 24 bits and no source joins
+        // later (the round field then counts from 0); room for 8-byte
+        // entries either way, for the rerun after a round overflow
+        G.narrow = (!joinable && n <= ((int64_t)1 << 24)) ? 1u : 0u;
+        G.E = (void*)p; p += al256((size_t)n * G.k * 8);
         for (size_t j = 0; j < gq.size(); ++j) {
             hsrc[(size_t)i * 64 + j] = (uint32_t)qs[gq[j]].src;
             rowsD[(size_t)i * 64 + j] = qs[gq[j]].dist;
@@ -978,13 +1050,13 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
             hipLaunchKernelGGL(ms_init_kernel, dim3(ig), dim3(kBlock), 0, stream, dgroups, i,
                                dsrcs + (size_t)i * 64, k);
             hipLaunchKernelGGL(ms_seed_kernel, dim3(1), dim3(64), 0, stream, dgroups, i,
-                               dsrcs + (size_t)i * 64, k);
+                               dsrcs + (size_t)i * 64, k, i == 0 ? dovf : nullptr);
         }
         return hipGetLastError();
     };
-    GB_HIP(init_groups());
     MsArgs A;
     A.groups = dgroups;
+    A.ovf = dovf;
     A.ngroups = NG;
     A.force_dir = o.force_direction == 3 ? 0 : o.force_direction;
     A.light = o.pull_light;
@@ -993,77 +1065,101 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     int64_t work = 0;
     for (int i = 0; i < NG; ++i) work += std::max<int64_t>(hg[i].n / 64, 1);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((work + kRWaves - 1) / kRWaves, o.grid));
-    uint32_t r = 0;
-    int64_t round_limit = maxn + 2;
     unsigned long long* hp = (unsigned long long*)pin;
-    bool done = false;
-    if (o.persistent > 0 && !joinable) {
-        // every round in one cooperative launch; if the launch is refused or
-        // a barrier wait gave up, the groups start again one launch per round
-        GB_TRY(ms_run_persistent(A, dbar, grid, qs[groups[gb0][0]].g, round_limit, hp, stream,
-                                 &done, &r));
-        if (done) {
-            *launches_out += 1;
-        } else {
-            r = 0;
-            GB_HIP(init_groups());
-        }
-    }
-    // rounds here take milliseconds: a completion check per batch is cheap;
-    // a group that admits arrivals checks every 4 rounds
-    int K = joinable ? 4 : 8;
+    bool narrow = false;
+    for (int i = 0; i < NG; ++i) narrow |= hg[i].narrow != 0u;
+    uint32_t r = 0;
     uint32_t kused = hg[0].kused;
-    while (!done) {
-        for (int i = 0; i < K; ++i)
-            hipLaunchKernelGGL(ms_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, A, r + i);
-        GB_HIP(hipGetLastError());
-        r += (uint32_t)K;
-        *launches_out += K;
-        for (int i = 0; i < NG; ++i)
-            GB_HIP(hipMemcpyAsync(hp + (size_t)i * kSpread * kSpreadStride,
-                                  hg[i].ctl + 8 + (size_t)(r & 3u) * kSpread * kSpreadStride,
-                                  kSpread * kSpreadStride * 8, hipMemcpyDeviceToHost, stream));
-        GB_HIP(hipStreamSynchronize(stream));
-        bool active = false;
-        for (int i = 0; i < NG && !active; ++i) {
-            unsigned long long t = 0;
-            for (int c = 0; c < kSpread; ++c) t += hp[(size_t)i * kSpread * kSpreadStride + c * kSpreadStride];
-            active = (t >> 32) != 0;
-        }
-        if (joinable && kused < hg[0].k) {
-            // round boundary r: queries waiting for this graph join the group
-            std::vector<MsQuery> add;
-            (*hook)(r, (int)(hg[0].k - kused), !active, &add);
-            if (!add.empty()) {
-                const uint32_t nadd = (uint32_t)std::min<size_t>(add.size(), hg[0].k - kused);
-                for (uint32_t i = 0; i < nadd; ++i) {
-                    hsrc[kused + i] = (uint32_t)add[i].src;
-                    rowsD[kused + i] = add[i].dist;
-                    rowsP[kused + i] = add[i].parent;
-                }
-                GB_HIP(hipMemcpyAsync((void*)(hg[0].drow + kused), &rowsD[kused], nadd * 8,
-                                      hipMemcpyHostToDevice, stream));
-                GB_HIP(hipMemcpyAsync((void*)(hg[0].prow + kused), &rowsP[kused], nadd * 8,
-                                      hipMemcpyHostToDevice, stream));
-                GB_HIP(hipMemcpyAsync(dsrcs + kused, &hsrc[kused], nadd * 4,
-                                      hipMemcpyHostToDevice, stream));
-                if (!active) {
-                    const int cg = (int)std::min<int64_t>(
-                        std::max<int64_t>((hg[0].n + kBlock - 1) / kBlock, 1), 4096);
-                    hipLaunchKernelGGL(ms_clear_frontiers_kernel, dim3(cg), dim3(kBlock), 0, stream,
-                                       dgroups, 0);
-                }
-                hipLaunchKernelGGL(ms_join_kernel, dim3(1), dim3(64), 0, stream, dgroups, 0, r,
-                                   dsrcs + kused, kused, nadd);
-                GB_HIP(hipGetLastError());
-                kused += nadd;
-                round_limit = (int64_t)r + maxn + 2;
-                active = true;
+    // every round of every group, from the sources
+    auto run_rounds = [&]() -> int {
+        GB_HIP(init_groups());
+        r = 0;
+        int64_t round_limit = maxn + 2;
+        bool done = false;
+        if (o.persistent > 0 && !joinable) {
+            // every round in one cooperative launch; if the launch is refused or
+            // a barrier wait gave up, the groups start again one launch per round
+            GB_TRY(ms_run_persistent(A, dbar, grid, qs[groups[gb0][0]].g, round_limit, hp, stream,
+                                     &done, &r));
+            if (done) {
+                *launches_out += 1;
+            } else {
+                r = 0;
+                GB_HIP(init_groups());
             }
         }
-        if (!active) break;
-        if ((int64_t)r > round_limit) return set_error(GBGPU_E_HIP, "batched BFS did not terminate");
-        if (!joinable) K = std::min(K * 2, 512);
+        // rounds here take milliseconds: a completion check per batch is cheap;
+        // a group that admits arrivals checks every 4 rounds
+        int K = joinable ? 4 : 8;
+        while (!done) {
+            for (int i = 0; i < K; ++i)
+                hipLaunchKernelGGL(ms_round_kernel, dim3(grid), dim3(kRBlock), 0, stream, A, r + i);
+            GB_HIP(hipGetLastError());
+            r += (uint32_t)K;
+            *launches_out += K;
+            for (int i = 0; i < NG; ++i)
+                GB_HIP(hipMemcpyAsync(hp + (size_t)i * kSpread * kSpreadStride,
+                                      hg[i].ctl + 8 + (size_t)(r & 3u) * kSpread * kSpreadStride,
+                                      kSpread * kSpreadStride * 8, hipMemcpyDeviceToHost, stream));
+            GB_HIP(hipStreamSynchronize(stream));
+            bool active = false;
+            for (int i = 0; i < NG && !active; ++i) {
+                unsigned long long t = 0;
+                for (int c = 0; c < kSpread; ++c)
+                    t += hp[(size_t)i * kSpread * kSpreadStride + c * kSpreadStride];
+                active = (t >> 32) != 0;
+            }
+            if (joinable && kused < hg[0].k) {
+                // round boundary r: queries waiting for this graph join the group
+                std::vector<MsQuery> add;
+                (*hook)(r, (int)(hg[0].k - kused), !active, &add);
+                if (!add.empty()) {
+                    const uint32_t nadd = (uint32_t)std::min<size_t>(add.size(), hg[0].k - kused);
+                    for (uint32_t i = 0; i < nadd; ++i) {
+                        hsrc[kused + i] = (uint32_t)add[i].src;
+                        rowsD[kused + i] = add[i].dist;
+                        rowsP[kused + i] = add[i].parent;
+                    }
+                    GB_HIP(hipMemcpyAsync((void*)(hg[0].drow + kused), &rowsD[kused], nadd * 8,
+                                          hipMemcpyHostToDevice, stream));
+                    GB_HIP(hipMemcpyAsync((void*)(hg[0].prow + kused), &rowsP[kused], nadd * 8,
+                                          hipMemcpyHostToDevice, stream));
+                    GB_HIP(hipMemcpyAsync(dsrcs + kused, &hsrc[kused], nadd * 4,
+                                          hipMemcpyHostToDevice, stream));
+                    if (!active) {
+                        const int cg = (int)std::min<int64_t>(
+                            std::max<int64_t>((hg[0].n + kBlock - 1) / kBlock, 1), 4096);
+                        hipLaunchKernelGGL(ms_clear_frontiers_kernel, dim3(cg), dim3(kBlock), 0,
+                                           stream, dgroups, 0);
+                    }
+                    hipLaunchKernelGGL(ms_join_kernel, dim3(1), dim3(64), 0, stream, dgroups, 0, r,
+                                       dsrcs + kused, kused, nadd);
+                    GB_HIP(hipGetLastError());
+                    kused += nadd;
+                    round_limit = (int64_t)r + maxn + 2;
+                    active = true;
+                }
+            }
+            if (!active) break;
+            if ((int64_t)r > round_limit)
+                return set_error(GBGPU_E_HIP, "batched BFS did not terminate");
+            if (!joinable) K = std::min(K * 2, 512);
+        }
+        return GBGPU_OK;
+    };
+    GB_TRY(run_rounds());
+    if (narrow) {
+        uint32_t ovf = 0;
+        GB_HIP(hipMemcpyAsync(&ovf, dovf, 4, hipMemcpyDeviceToHost, stream));
+        GB_HIP(hipStreamSynchronize(stream));
+        if (ovf) {
+            // a search ran past round kNarrowRounds: every group again with
+            // 8-byte entries
+            for (int i = 0; i < NG; ++i) hg[i].narrow = 0u;
+            GB_HIP(hipMemcpyAsync(dgroups, hg.data(), sizeof(MsGroupDev) * NG,
+                                  hipMemcpyHostToDevice, stream));
+            GB_TRY(run_rounds());
+        }
     }
     for (int i = 0; i < NG; ++i) {
         const int tg = (int)std::min<int64_t>(std::max<int64_t>((hg[i].n + 63) / 64, 1), 8192);

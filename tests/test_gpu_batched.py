@@ -130,6 +130,39 @@ def test_deep_graphs_batch_one_source_at_a_time(gb):
         assert np.array_equal(parents[q].cpu().numpy(), op), q
 
 
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_batched_rounds_past_the_narrow_round_field(gb, persistent):
+    """A group on a graph of at most 2^24 vertices keeps each (vertex,
+    source) pair in 4 bytes with an 8-bit round of arrival.  Fresh handles
+    (depth unknown, so the sources are batched): a 255-vertex path from one
+    end reaches distance 254 within the field; a 256-vertex path and a
+    1200-cycle run past round 254, stop, and the call runs again with 8-byte
+    entries, also for the shallow graph batched beside them.  Every row
+    equals the oracle."""
+    opts = {"persistent": persistent}
+    for n in (255, 256):
+        h = gg.path(n)
+        G = gb.Graph.from_csr(h)
+        srcs = [0, n - 1, n // 2, 0]
+        D, P = gb.bfs_multi(G, srcs, opts=opts)
+        check_rows(h, srcs, D, P, tag=f"path{n}")
+        assert int(D[0].max()) == n - 1
+        G.free()
+    deep, shallow = gg.cycle(1200), gg.rmat(10, seed=5)
+    Gd, Gs = gb.Graph.from_csr(deep), gb.Graph.from_csr(shallow)
+    ss = [int(x) for x in gg.sources(shallow, 3, seed=2)]
+    graphs = [deep, shallow, deep, shallow, shallow]
+    qg = [Gd, Gs, Gd, Gs, Gs]
+    qs = [3, ss[0], 700, ss[1], ss[2]]
+    dists, parents = gb.bfs_batch(qg, qs, opts=opts)
+    for q, (h, s) in enumerate(zip(graphs, qs)):
+        od, op = oracle.bfs(h, s)
+        assert np.array_equal(dists[q].cpu().numpy(), od), q
+        assert np.array_equal(parents[q].cpu().numpy(), op), q
+    Gd.free()
+    Gs.free()
+
+
 @pytest.mark.parametrize("join_round", [0, 5, 9, 40])
 def test_sources_joining_a_running_group(gb, rmat14, join_round):
     """Round-boundary admission: srcs[:5] start a packed group, the rest join
