@@ -34,9 +34,6 @@ constexpr uint32_t kNarrowRounds = 254;
 // 64-edge windows a wavefront of the dense scan loads before it updates
 constexpr int kMsWin = 2;
 
-int run_bfs(gbgpu_graph g, int32_t src, int32_t* dist, int32_t* parent, const gbgpu_opts& o,
-            gbgpu_stats* st, hipStream_t stream);
-
 struct MsGroupDev {
     const int64_t* off;
     const int32_t* nbr;
@@ -71,7 +68,7 @@ __device__ __host__ __forceinline__ uint32_t* ent32(const MsGroupDev& G) { retur
 
 struct MsArgs {
     MsGroupDev* groups;
-    uint32_t* ovf;   // set when a narrow group reached round kNarrowRounds + 1
+    unsigned long long* ovf;  // bit gi: narrow group gi reached round kNarrowRounds + 1
     int32_t ngroups;
     int32_t force_dir;
     int32_t light;
@@ -133,10 +130,10 @@ __global__ __launch_bounds__(kBlock) void ms_init_kernel(MsGroupDev* groups, int
 // sources' own entries (distance 0, parent itself, visited) are set here so
 // that an isolated source needs no traversal work.
 __global__ void ms_seed_kernel(MsGroupDev* groups, int32_t gi, const uint32_t* srcs, int32_t k,
-                               uint32_t* ovf) {
+                               unsigned long long* ovf) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const MsGroupDev G = groups[gi];
-    if (ovf) *ovf = 0u;
+    if (ovf) *ovf = 0ull;
     uint32_t cnt = 0, edges = 0;
     for (int j = 0; j < k; ++j) {
         const uint32_t s = srcs[j];
@@ -737,7 +734,7 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
                 // the host runs the call again with 8-byte entries
                 t = 0ull;
                 s_tot[gi] = 0ull;
-                if (blockIdx.x == 0) *A.ovf = 1u;
+                if (blockIdx.x == 0) *A.ovf |= 1ull << gi;
             }
             const uint32_t cnt = (uint32_t)(t >> 32), edges = (uint32_t)t;
             const bool qvalid = G.ctl[4 + (r & 3u)] == 0ull;
@@ -921,7 +918,7 @@ static std::vector<std::vector<int>> ms_plan(const std::vector<MsQuery>& qs) {
 
 static size_t ms_header_bytes(int NG) {
     return al256(sizeof(MsGroupDev) * NG) + al256((size_t)NG * 64 * 4) +
-           al256(4096 * kMaxGroups * 4) + al256((size_t)kBarWords * 4) + al256(4);
+           al256(4096 * kMaxGroups * 4) + al256((size_t)kBarWords * 4) + al256(8);
 }
 
 // Device bytes needed to run `groups` (at most kMaxGroups) together.
@@ -997,7 +994,7 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     uint32_t* dsrcs = (uint32_t*)p; p += al256((size_t)NG * 64 * 4);
     uint32_t* dlog = (uint32_t*)p; p += al256(4096 * kMaxGroups * 4);
     uint32_t* dbar = (uint32_t*)p; p += al256((size_t)kBarWords * 4);
-    uint32_t* dovf = (uint32_t*)p; p += al256(4);
+    unsigned long long* dovf = (unsigned long long*)p; p += al256(8);
     std::vector<MsGroupDev> hg(NG);
     std::vector<uint32_t> hsrc((size_t)NG * 64, 0);
     std::vector<int32_t*> rowsD((size_t)NG * 64, nullptr), rowsP((size_t)NG * 64, nullptr);
@@ -1027,10 +1024,13 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         G.start = (uint32_t*)p; p += al256(64 * 4);
         G.k = (uint32_t)std::max<size_t>(gq.size(), joinable ? kcap : 0u);
         G.kused = (uint32_t)gq.size();
-        // 4-byte entries where a parent fits in 24 bits and no source joins
-        // later (the round field then counts from 0); room for 8-byte
-        // entries either way, for the rerun after a round overflow
-        G.narrow = (!joinable && n <= ((int64_t)1 << 24)) ? 1u : 0u;
+        // 4-byte entries where a parent fits in 24 bits, no source joins
+        // later (the round field then counts from 0) and no search has shown
+        // the graph deeper than the field; room for 8-byte entries either
+        // way, for the rerun after a round overflow
+        G.narrow = (!joinable && n <= ((int64_t)1 << 24) &&
+                    g->depth.load(std::memory_order_relaxed) <= (int32_t)kNarrowRounds)
+                       ? 1u : 0u;
         G.E = (void*)p; p += al256((size_t)n * G.k * 8);
         for (size_t j = 0; j < gq.size(); ++j) {
             hsrc[(size_t)i * 64 + j] = (uint32_t)qs[gq[j]].src;
@@ -1149,13 +1149,24 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
     };
     GB_TRY(run_rounds());
     if (narrow) {
-        uint32_t ovf = 0;
-        GB_HIP(hipMemcpyAsync(&ovf, dovf, 4, hipMemcpyDeviceToHost, stream));
+        unsigned long long ovf = 0;
+        GB_HIP(hipMemcpyAsync(&ovf, dovf, 8, hipMemcpyDeviceToHost, stream));
         GB_HIP(hipStreamSynchronize(stream));
         if (ovf) {
-            // a search ran past round kNarrowRounds: every group again with
-            // 8-byte entries
-            for (int i = 0; i < NG; ++i) hg[i].narrow = 0u;
+            // a search ran past round kNarrowRounds: its graph is marked that
+            // deep (later calls start with 8-byte entries), and every group
+            // runs again with 8-byte entries
+            for (int i = 0; i < NG; ++i) {
+                if ((ovf >> i) & 1ull) {
+                    gbgpu_graph g = qs[groups[gb0 + i][0]].g;
+                    int32_t d = g->depth.load(std::memory_order_relaxed);
+                    while (d <= (int32_t)kNarrowRounds &&
+                           !g->depth.compare_exchange_weak(d, (int32_t)kNarrowRounds + 1,
+                                                           std::memory_order_relaxed)) {
+                    }
+                }
+                hg[i].narrow = 0u;
+            }
             GB_HIP(hipMemcpyAsync(dgroups, hg.data(), sizeof(MsGroupDev) * NG,
                                   hipMemcpyHostToDevice, stream));
             GB_TRY(run_rounds());
@@ -1219,27 +1230,6 @@ int run_ms_group_mem(const std::vector<MsQuery>& qs, void* mem, void* pin, const
     return ms_run_chunk(qs, groups, 0, 1, mem, pin, o, stream, rounds, &launches, kcap, hook);
 }
 
-// Queries answered one source at a time on each graph's own workspace
-// (lock_graphs: take each graph's lock, else the caller holds it).
-int run_singles(const std::vector<MsQuery>& qs, const gbgpu_opts& o, gbgpu_stats* st,
-                       hipStream_t stream, bool lock_graphs) {
-    int launches = 0, rounds = 0;
-    for (const MsQuery& q : qs) {
-        gbgpu_stats s1;
-        std::unique_lock<std::mutex> lk(q.g->mu, std::defer_lock);
-        if (lock_graphs) lk.lock();
-        GB_TRY(run_bfs(q.g, q.src, q.dist, q.parent, o, &s1, stream));
-        launches += s1.launches;
-        rounds = std::max(rounds, s1.rounds);
-    }
-    if (st) {
-        memset(st, 0, sizeof(*st));
-        st->launches = launches;
-        st->rounds = rounds;
-    }
-    return GBGPU_OK;
-}
-
 }  // namespace gb
 
 using namespace gb;
@@ -1259,8 +1249,6 @@ int gbgpu_bfs_multi(gbgpu_graph g, const int32_t* srcs, int32_t k, int32_t* dist
     for (int i = 0; i < k; ++i)
         qs[i] = MsQuery{g, srcs[i], dist + (size_t)i * g->n, parent + (size_t)i * g->n};
     std::lock_guard<std::mutex> lk(g->mu);
-    if (g->depth.load(std::memory_order_relaxed) > kDeepGraph)
-        return run_singles(qs, opt, st, (hipStream_t)stream, false);
     return run_ms(qs, opt, st, (hipStream_t)stream, &g->multi);
 }
 
@@ -1325,22 +1313,8 @@ int gbgpu_bfs_batch(const gbgpu_graph* graphs, const int32_t* srcs, int32_t nq,
         qs[i] = MsQuery{graphs[i], srcs[i], dists[i], parents[i]};
     }
     gbgpu_opts opt = resolve_opts(o);
-    // queries on graphs known to be deep run one at a time, the rest packed
-    std::vector<MsQuery> deep, packed;
-    for (const MsQuery& q : qs)
-        (q.g->depth.load(std::memory_order_relaxed) > kDeepGraph ? deep : packed).push_back(q);
-    gbgpu_stats s1, s2;
-    if (!deep.empty()) GB_TRY(run_singles(deep, opt, st ? &s1 : nullptr, (hipStream_t)stream, true));
-    if (!packed.empty()) {
-        std::lock_guard<std::mutex> lk(g_batch_mu);
-        GB_TRY(run_ms(packed, opt, st ? &s2 : nullptr, (hipStream_t)stream, &g_batch_ws));
-    }
-    if (st) {
-        memset(st, 0, sizeof(*st));
-        st->launches = (deep.empty() ? 0 : s1.launches) + (packed.empty() ? 0 : s2.launches);
-        st->rounds = std::max(deep.empty() ? 0 : s1.rounds, packed.empty() ? 0 : s2.rounds);
-    }
-    return GBGPU_OK;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    return run_ms(qs, opt, st, (hipStream_t)stream, &g_batch_ws);
 }
 
 }  // extern "C"

@@ -108,10 +108,12 @@ def test_batch_argument_errors(gb, rmat14):
         gb.bfs_multi(G, [])
 
 
-def test_deep_graphs_batch_one_source_at_a_time(gb):
-    """Once a single-source BFS has shown a graph to be deep, batched calls on
-    it answer each source on its own; mixed batches split between the two
-    paths.  Results equal the oracle either way."""
+def test_deep_graphs_batched(gb):
+    """Graphs a single-source BFS has shown to be deep are batched like any
+    other: the 300-cycle (151 levels) with 4-byte pair entries, the
+    600-cycle (301 levels, more than the 8-bit round field holds) with
+    8-byte entries from the start; mixed with a shallow graph in one batch.
+    Results equal the oracle."""
     deep, shallow = gg.cycle(300), gg.rmat(10, seed=5)
     Gd, Gs = gb.Graph.from_csr(deep), gb.Graph.from_csr(shallow)
     d0, p0, st = gb.bfs(Gd, 0, stats=True)
@@ -119,6 +121,14 @@ def test_deep_graphs_batch_one_source_at_a_time(gb):
     srcs = [0, 17, 150, 299]
     D, P = gb.bfs_multi(Gd, srcs)
     check_rows(deep, srcs, D, P, tag="deep multi")
+    deeper = gg.cycle(600)
+    Gdd = gb.Graph.from_csr(deeper)
+    _, _, st = gb.bfs(Gdd, 0, stats=True)
+    assert st["rounds"] == 301
+    srcs = [0, 1, 300, 599, 0]
+    D, P = gb.bfs_multi(Gdd, srcs)
+    check_rows(deeper, srcs, D, P, tag="deeper multi")
+    Gdd.free()
     ss = [int(x) for x in gg.sources(shallow, 3, seed=2)]
     graphs = [deep, shallow, deep, shallow, shallow]
     qg = [Gd, Gs, Gd, Gs, Gs]

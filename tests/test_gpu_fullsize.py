@@ -4,7 +4,8 @@
 * RMAT scale 24: BFS from the first two timed sources and weighted BFS
   (w < 24) from the first, element by element against the oracle; two rows
   of a 64-source batch against the oracle;
-* 256^3 torus: BFS against the closed form of distances and min-ID parents,
+* 256^3 torus: BFS, and 64 sources batched (rows 0, 31, 63), against the
+  closed form of distances and min-ID parents,
   weighted BFS (w < 24) against the definition-level checks;
 * general-weight SSSP and widest path (w < 24) from the first timed source:
   RMAT-24 against the oracle's Bellman-Ford and widest path, the torus
@@ -111,6 +112,25 @@ def test_torus256(gb):
     wd, wp = gb.wbfs(G, s, opts=tuned(prefix, "wbfs"))
     check_wbfs(g, s, gb.as_u32(wd), wp.cpu().numpy())
     G.free()
+
+
+def test_torus256_batched_rows(gb):
+    """64 sources on the 256^3 torus in one gbgpu_bfs_multi call, as the
+    benchmark times it: the graph is known to be 385 levels deep, so the pair
+    entries are 8 bytes from the start; rows 0, 31 and 63 against the closed
+    form."""
+    g = gg.torus3d(256)
+    G = gb.Graph.from_csr(g, validate=False, with_weights=False)
+    srcs = [int(x) for x in gg.sources(g, 64, seed=3)]
+    _, _, st = gb.bfs(G, srcs[0], stats=True)
+    assert st["rounds"] > 254
+    D, P = gb.bfs_multi(G, srcs)
+    for i in (0, 31, 63):
+        ed, ep = torus_closed_form(256, srcs[i])
+        assert_same(D[i].cpu().numpy(), P[i].cpu().numpy(), ed, ep, f"torus256 batched row {i}")
+    del D, P
+    G.free()
+    torch.cuda.empty_cache()
 
 
 def test_rmat24_bellman_ford_and_widest_path(gb, rmat24):
