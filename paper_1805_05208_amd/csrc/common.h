@@ -130,10 +130,11 @@ constexpr int kTauDefaulted = 0;
 int ensure_pull_plan(gbgpu_graph g);
 constexpr uint32_t kPlanCap = 1024;   // max edges of one dense-scan work item
 constexpr uint32_t kPlanHub = 0xFFFFFFFFu;
-// Graphs whose BFS depth exceeds this run batched BFS queries one source at
-// a time: with sources spread over a long diameter most vertices stay in
-// the union of the frontiers for many rounds, so bit-packed batching saves
-// little work and its pushes pay one parent atomicMin per source bit.
+// The server packs BFS queries only on graphs a search has shown to be at
+// most this deep: a packed group holds every query in it until its last
+// round, so on a long diameter the packed queries wait far longer than
+// queries run one at a time (batched calls on such graphs still pay off:
+// 64 sources on the 256^3 torus, 408 ms against 684 one at a time).
 constexpr int32_t kDeepGraph = 64;
 
 // Words of coherent pinned host memory that the traversal kernels write with

@@ -273,10 +273,11 @@ int gbgpu_server_create(void* arena, size_t arena_bytes, int32_t max_inflight, c
     if (sv->opts.max_pending > 0) sv->max_pending = (size_t)sv->opts.max_pending;
     // BFS queries are bit-packed only on graphs a single-source search has
     // shown to be shallow, and only up to 2^24 vertices; the others run one
-    // at a time (concurrently on the workers).  Deep graphs keep 64
-    // frontiers alive for most rounds; on RMAT scale 26, 64 bit-packed
-    // sources ran at 312 queries/s against 358 one at a time.  The graph
-    // list is only read under the server's lock.
+    // at a time (concurrently on the workers).  A packed group holds every
+    // query in it until its last round, hundreds of rounds on a deep graph;
+    // on RMAT scale 26, 64 bit-packed sources ran at 312 queries/s against
+    // 358 one at a time (measured with the earlier two-array staging).  The
+    // graph list is only read under the server's lock.
     sv->env.packable = [sv](int32_t gid) {
         gbgpu_graph g = sv->graphs[gid];
         const int32_t depth = g->depth.load(std::memory_order_relaxed);
