@@ -173,6 +173,39 @@ def test_batched_rounds_past_the_narrow_round_field(gb, persistent):
     Gs.free()
 
 
+def sparse_csr(n, edges, name):
+    """Symmetric CSR of a few undirected edges over n vertices (numpy only,
+    for n in the millions)."""
+    e = np.asarray(edges, dtype=np.int64)
+    us = np.concatenate([e[:, 0], e[:, 1]])
+    vs = np.concatenate([e[:, 1], e[:, 0]])
+    order = np.lexsort((vs, us))
+    us, vs = us[order], vs[order]
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(offsets, us + 1, 1)
+    return gg.CSR(n=n, offsets=np.cumsum(offsets), nbrs=vs.astype(np.int32), name=name)
+
+
+@pytest.mark.parametrize("n", [1 << 24, (1 << 24) + 1])
+def test_batched_parents_at_the_24_bit_limit(gb, n):
+    """4-byte pair entries keep a 24-bit parent: with n = 2^24 (the largest
+    graph that uses them) vertex 2^24 - 1 is a hub and a parent; with
+    n = 2^24 + 1 the entries are 8 bytes and vertex 2^24 is a parent.  A few
+    edges among low and high ids; every row equals the oracle."""
+    top = n - 1
+    edges = [(0, 1), (1, 2), (2, 3), (top, 0), (top, top - 1), (top, 7), (top - 1, 5), (5, 6),
+             (3, 4), (top - 2, top - 1)]
+    h = sparse_csr(n, edges, f"sparse{n}")
+    G = gb.Graph.from_csr(h, with_weights=False)
+    srcs = [top, 3, top - 1, 6, 0]
+    D, P = gb.bfs_multi(G, srcs)
+    check_rows(h, srcs, D, P, tag=f"n={n}")
+    assert int(P[1][top]) == 0 and int(P[3][7]) == top
+    del D, P
+    G.free()
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("join_round", [0, 5, 9, 40])
 def test_sources_joining_a_running_group(gb, rmat14, join_round):
     """Round-boundary admission: srcs[:5] start a packed group, the rest join
