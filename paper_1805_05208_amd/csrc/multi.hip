@@ -1,5 +1,11 @@
 // Batched BFS: many sources, possibly on many graphs, in one launch per round.
 //
+// The paper's strongly-connected-components algorithm runs the searches
+// from all active centers simultaneously, one edgeMap per round, each
+// search adding in every round exactly the labels it would add alone, and
+// keeps the first phase's reachability in bit-vectors; here the labels are
+// the bits of a per-vertex mask, one bit per source.
+//
 // Sources are packed 64 to a group; a group is (graph, up to 64 sources) and
 // every vertex of the group's graph carries three 64-bit masks: visited VM,
 // frontier F_r and next frontier F_{r+1} (bit j = source j).  One launch per
@@ -17,8 +23,9 @@
 //     scans one list), with early exit once every unseen bit is found.
 // Both rules give parent_j[v] = min{u in N(v) : D_j[u] = D_j[v] - 1}, so each
 // row equals the single-source BFS from source j.  A pair (v, j) is written
-// once, in the round r that finds it, as one 64-bit entry (arrival round
-// r + 1, parent): D_j[v] = r + 1, the round whose frontier holds bit j of v.
+// once, in the round r that finds it, as one entry (arrival round r + 1,
+// parent; 4 or 8 bytes, see MsGroupDev::E): D_j[v] = r + 1, the round whose
+// frontier holds bit j of v.
 // Groups finish independently; a finished group costs nothing.
 
 #include "common.h"
