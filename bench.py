@@ -221,6 +221,8 @@ def main():
                     help="queries the server keeps on the device at once (worker streams)")
     ap.add_argument("--serving-queries", type=int, default=2000,
                     help="Poisson arrivals per offered load in the serving section")
+    ap.add_argument("--torus", action="store_true",
+                    help="with --only batched: the 256^3 torus instead of RMAT")
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuned options in paper_1805_05208_amd/tuned.json")
     ap.add_argument("--only", choices=["connectivity", "compressed", "wbfs", "sssp", "bc",
@@ -238,6 +240,8 @@ def main():
         segments(args.segments, args.start, args.kernel, args.segment, args.step_log,
                  args.counter)
         return
+    if args.torus and args.only != "batched":
+        ap.error("--torus goes with --only batched")
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding a query over several GPUs is a design, not code that runs.", file=sys.stderr)
@@ -255,9 +259,10 @@ def main():
     tuned_path = TUNED
 
     t = time.time()
-    g = gg.rmat(args.scale, seed=1)
+    gname = "torus256" if args.torus else f"rmat{args.scale}"
+    g = gg.torus3d(256) if args.torus else gg.rmat(args.scale, seed=1)
     srcs = [int(s) for s in gg.sources(g, args.sources, seed=3)]
-    log(f"generated rmat{args.scale}: n={g.n} m={g.m} in {time.time() - t:.1f}s")
+    log(f"generated {gname}: n={g.n} m={g.m} in {time.time() - t:.1f}s")
     G = gb.Graph.from_csr(g, validate=False, with_weights=False)
     deg = g.degrees()
     stream = torch.cuda.current_stream()
@@ -343,8 +348,7 @@ def main():
         D, P = gb.bfs_multi(G, s64)
         d1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
         p1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        res = {"metric": "batched_section", "config": {"workload": f"rmat{args.scale}",
-                                                       "sources": 64}}
+        res = {"metric": "batched_section", "config": {"workload": gname, "sources": 64}}
         for key, fn in (("batched64", lambda: gb.bfs_multi(G, s64, dist=D, parent=P)),
                         ("single", lambda: [gb.bfs(G, s, dist=d1, parent=p1) for s in s64])):
             for _ in range(args.warmup):

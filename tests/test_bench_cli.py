@@ -15,6 +15,13 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
+def test_torus_goes_with_the_batched_section():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--torus"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--torus goes with --only batched" in r.stderr
+
+
 def test_pmc_summary_reads_a_counter_csv(tmp_path):
     rows = [
         "Correlation_Id,Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value",
