@@ -38,8 +38,13 @@ constexpr int kMaxGroups = 64;
 // last round a group with 4-byte pair entries may run (its arrivals, at most
 // this round + 1, fill the 8-bit round field)
 constexpr uint32_t kNarrowRounds = 254;
-// 64-edge windows a wavefront of the dense scan loads before it updates
+// 64-edge windows a wavefront of the dense scan loads before it updates: 2,
+// or 6 on graphs of average degree at most 8, where a 64-vertex run's edges
+// then come in one step (256^3 torus, 64 sources: 375 against 408 ms; on
+// RMAT-24 six windows cost 19.5 against 18.9 ms, the early exits coming a
+// step later)
 constexpr int kMsWin = 2;
+constexpr int kMsWinSparse = 6;
 
 struct MsGroupDev {
     const int64_t* off;
@@ -47,6 +52,7 @@ struct MsGroupDev {
     const uint32_t* deg;
     int64_t n;
     uint64_t dense_thresh;
+    uint64_t m;                 // stored edges
     unsigned long long kmask;   // bits of the sources in this group (kused of them)
     unsigned long long* VM;     // n
     unsigned long long* F[3];   // n each
@@ -506,6 +512,7 @@ __device__ __forceinline__ void wave_store_bits(unsigned long long bits, T* row,
 // prefix-OR over the lanes of each vertex gives first contributors within a
 // window, and a per-vertex accumulator carries earlier windows.  A vertex
 // stops being scanned once all its unseen bits are found.
+template <int W>
 __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uint4 it,
                                             const unsigned long long* __restrict__ Fc,
                                             unsigned long long* Fn, MsEmitter& em,
@@ -549,21 +556,21 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
             e = max(e, __shfl(s, first_lane(after), 64));
             continue;
         }
-        // kMsWin windows: owners, then all loads, then the ordered updates
-        int ow[kMsWin];
-        uint32_t u[kMsWin];
-        unsigned long long fu[kMsWin];
+        // W windows: owners, then all loads, then the ordered updates
+        int ow[W];
+        uint32_t u[W];
+        unsigned long long fu[W];
 #pragma unroll
-        for (int k = 0; k < kMsWin; ++k) {
+        for (int k = 0; k < W; ++k) {
             const uint32_t t = e + 64u * k + (uint32_t)l;
             ow[k] = owner(t);
             const bool act = t < T && ((live >> ow[k]) & 1ull);
             u[k] = act ? (uint32_t)G.nbr[base + t] : kNone;
         }
 #pragma unroll
-        for (int k = 0; k < kMsWin; ++k) fu[k] = u[k] != kNone ? Fc[u[k]] : 0ull;
+        for (int k = 0; k < W; ++k) fu[k] = u[k] != kNone ? Fc[u[k]] : 0ull;
 #pragma unroll
-        for (int k = 0; k < kMsWin; ++k) {
+        for (int k = 0; k < W; ++k) {
             const uint32_t eb = e + 64u * k;
             if (eb >= T) break;
             const int o = ow[k];
@@ -601,7 +608,7 @@ __device__ __forceinline__ void ms_pull_run(const MsGroupDev& G, uint32_t r, uin
             if (hasw) acc |= tot;
         }
         live = ballot(need != 0ull && acc != need);
-        e += 64u * kMsWin;
+        e += 64u * W;
     }
     const bool got = acc != 0ull;
     if (in && got) {
@@ -701,6 +708,9 @@ __device__ __forceinline__ QueueOut ms_next_list(const MsGroupDev& G, uint32_t r
 
 // One round r for every group (workgroup-uniform); returns false when no
 // group has a frontier in round r (every group has finished).
+// kSparseWin: the one-launch-per-round kernel picks kMsWinSparse windows on
+// sparse graphs; the persistent kernel keeps kMsWin (its registers are full).
+template <bool kSparseWin>
 __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& sh) {
     uint32_t* s_units = sh.units;
     uint32_t* s_push = sh.push;
@@ -837,10 +847,13 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
             }
         } else {
             const uint4 it = G.plan[local];
-            if (it.z == kPlanHub)
-                ms_pull_run(G, r, it, Fc, Fn, em, out, s_emit[gi] != 0, f0, d0);
+            const bool emit = s_emit[gi] != 0;
+            if (it.z != kPlanHub)
+                ms_pull_piece(G, r, it, Fc, Fn, em, out, emit, f0, d0);
+            else if (kSparseWin && G.m <= 8ull * (uint64_t)G.n)
+                ms_pull_run<kMsWinSparse>(G, r, it, Fc, Fn, em, out, emit, f0, d0);
             else
-                ms_pull_piece(G, r, it, Fc, Fn, em, out, s_emit[gi] != 0, f0, d0);
+                ms_pull_run<kMsWin>(G, r, it, Fc, Fn, em, out, emit, f0, d0);
         }
         f0 = wave_sum(f0);
         d0 = wave_sum(d0);
@@ -863,7 +876,7 @@ __device__ __forceinline__ bool ms_round(const MsArgs& A, uint32_t r, MsShared& 
 
 __global__ __launch_bounds__(kRBlock, 1) void ms_round_kernel(MsArgs A, uint32_t r) {
     __shared__ MsShared sh;
-    (void)ms_round(A, r, sh);
+    (void)ms_round<true>(A, r, sh);
 }
 
 // Every round of every group in one cooperative launch, a grid barrier
@@ -878,7 +891,7 @@ __global__ __launch_bounds__(kRBlock, 1) void ms_persistent_kernel(MsArgs A, uin
     if (!bar_census(bar, di)) return;
     uint32_t r = 0;
     for (; r < max_rounds; ++r) {
-        if (!ms_round(A, r, sh)) break;
+        if (!ms_round<false>(A, r, sh)) break;
         if (!grid_barrier(bar, di, r + 1)) return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) bar[kBarUser] = r;
@@ -1017,6 +1030,7 @@ static int ms_run_chunk(const std::vector<MsQuery>& qs, const std::vector<std::v
         G.deg = g->deg;
         G.n = n;
         G.dense_thresh = (uint64_t)g->m / (uint64_t)o.tau;
+        G.m = (uint64_t)g->m;
         G.kmask = gq.size() == 64 ? ~0ull : ((1ull << gq.size()) - 1ull);
         GB_TRY(ensure_pull_plan(g));
         G.plan = g->plan;
