@@ -371,7 +371,7 @@ int gbgpu_bfs_multi(gbgpu_graph g, const int32_t* srcs, int32_t k,
  * launch instead, a grid barrier between rounds, ending at the first round
  * in which no group has a frontier (st->launches then counts one launch per
  * 64 groups).  Graphs of any depth are batched (on RMAT-24 and the 256^3
- * torus 64 batched sources run 1.5x and 1.7x faster than one at a time).
+ * torus 64 batched sources run 1.5x and 1.8x faster than one at a time).
  *   graphs   host array of nq graph handles (repeats allowed, any sizes)
  *   srcs     host int32[nq]
  *   dists    host array of nq dev int32* outputs (each n_i long)
